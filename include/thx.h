@@ -1,0 +1,145 @@
+/*
+ * thx.h -- C ABI of libthx: fast polynomial basis conversion  beta = A alpha
+ * on AMD Instinct MI355X (gfx950), following Townsend, Webb & Olver, "Fast
+ * polynomial transforms based on Toeplitz and Hankel matrices" (arXiv:1604.07486).
+ *
+ * The conversion matrix is written A = D1 (T o H) D2 (eq. HadamardDecomposition),
+ * the Hankel factor H is replaced by a rank-K pivoted-Cholesky approximation
+ * (Sec. 2.1, Fig. 3) and each of the K diagonally scaled Toeplitz products of
+ * eq. (Cdecomposition) is evaluated with FFTs (Fig. 1, steps 3-5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A polynomial of degree N has N+1 coefficients; coefficient vectors are rows
+ *   of a row-major [batch][ld] array of doubles with ld >= N+1.  alpha and beta
+ *   are DEVICE pointers owned by the caller; beta must not overlap alpha.
+ * - All device work is ordered on `stream` (a hipStream_t; 0 = null stream).
+ *   Only plan creation synchronises the stream (once, to read the rank K).
+ * - No exception or abort crosses this boundary: every call returns a
+ *   thx_status.  On THX_HIP_ERROR, thx_last_hip_error() holds the hipError_t.
+ * - Plans are immutable after creation; one plan may be executed concurrently
+ *   on different streams only if each execution uses its own workspace, which
+ *   this library does not provide: serialise executions of a plan.
+ */
+#ifndef THX_H
+#define THX_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    THX_OK = 0,
+    THX_INVALID_ARGUMENT = 1, /* bad size, parameter, tolerance or null pointer   */
+    THX_UNSUPPORTED = 2,      /* parameters outside the implemented cases         */
+    THX_TOL_NOT_REACHED = 3,  /* pivoted Cholesky hit its rank cap before tol;
+                                 the plan is still created and usable            */
+    THX_OUT_OF_MEMORY = 4,    /* device or host allocation failed                  */
+    THX_HIP_ERROR = 5         /* a HIP runtime call failed                         */
+} thx_status;
+
+typedef enum {
+    THX_LEG2CHEB = 0,    /* Legendre -> Chebyshev, eq. (M), Sec. 3                     */
+    THX_CHEB2LEG = 1,    /* Chebyshev -> Legendre, eq. (FormulaL), Sec. 5.1            */
+    THX_ULTRA2ULTRA = 2, /* C^(l1) -> C^(l2), eq. (UltraSconversion), Sec. 5.2          */
+    THX_JAC2JAC = 3,     /* P^(a,b) -> P^(g,b) (same second parameter), Sec. 5.3 case 2 */
+    THX_LAG2LAG = 4      /* L^(a1) -> L^(a2), Sec. 5.4                                  */
+} thx_kind;
+
+typedef enum {
+    THX_FP64 = 0,      /* every step in double precision                              */
+    THX_FP32_BULK = 1  /* FFTs and rank accumulation in single precision; Lambda and
+                          Gamma ratios, the pivoted Cholesky and D1, D2 in double     */
+} thx_precision;
+
+/* plan flags */
+#define THX_FLAG_FORCE_DIRECT 1u /* always use the O(N^2) direct evaluation         */
+#define THX_FLAG_FORCE_FFT 2u    /* never use the direct evaluation (testing)        */
+
+typedef struct thx_plan thx_plan;
+
+/* Plan for converting polynomials of degree <= `degree` (Fig. 1 steps 1-2 and the
+ * symbol FFT): fills the Lambda / Gamma-ratio tables, runs the pivoted Cholesky
+ * of the Hankel part(s) to relative tolerance `tol` (stop when the largest
+ * residual diagonal entry is <= tol * max diag(H); Sec. 2.1 leaves the rule
+ * open), and transforms the Toeplitz symbol.  The plan may be reused for any
+ * number of executions (Sec. 2.1, last paragraph).
+ *   params / nparams: kind parameters -- ULTRA2ULTRA (l1, l2) with l1, l2 > 0;
+ *   JAC2JAC (a, b, g) with a, b, g > -1, |a - g| < 1 and a + b > -1;
+ *   LAG2LAG (a1, a2) with a1, a2 > -1.  LEG2CHEB / CHEB2LEG take none.
+ *   degree >= 0; 0 < tol < 1; flags: THX_FLAG_*.
+ * On success *out owns device memory until thx_plan_destroy.  Errors:
+ * THX_INVALID_ARGUMENT (out == NULL, degree < 0, tol outside (0,1), bad params),
+ * THX_UNSUPPORTED (parameters outside the implemented cases), THX_OUT_OF_MEMORY,
+ * THX_HIP_ERROR.  THX_TOL_NOT_REACHED returns a usable plan. */
+thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, int nparams,
+                           int64_t degree, double tol, thx_precision prec, uint32_t flags,
+                           hipStream_t stream);
+
+/* beta[b][0..N] = A alpha[b][0..N] for b < batch (Fig. 1 steps 3-5), N = degree
+ * with 0 <= degree <= the plan's degree.  alpha, beta: device doubles, row stride
+ * ld >= degree+1; entries beyond N in each row are neither read nor written.
+ * Errors: THX_INVALID_ARGUMENT (null plan, null pointers with batch > 0,
+ * degree out of range, ld too small, batch < 0), THX_HIP_ERROR. */
+thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
+                       int64_t batch, int64_t ld, hipStream_t stream);
+
+/* Release a plan (synchronises nothing; the caller must ensure no execution of
+ * it is still running).  NULL is accepted. */
+thx_status thx_plan_destroy(thx_plan *plan);
+
+/* Plan introspection (host values; no device work).
+ * rank: number of FFT slots K (for parity-split kinds max(K_even, K_odd)).
+ * rank_part: rank of Hankel part `part` (0 = even / only, 1 = odd), -1 if absent.
+ * fft_length: circulant-embedding length L (0 on the direct path).
+ * path: 0 direct, 1 single-workgroup LDS FFT, 2 three-pass FFT. */
+int32_t thx_plan_rank(const thx_plan *plan);
+int32_t thx_plan_rank_part(const thx_plan *plan, int part);
+int64_t thx_plan_fft_length(const thx_plan *plan);
+int32_t thx_plan_path(const thx_plan *plan);
+/* Largest residual diagonal entry of part `part` at termination, relative to
+ * max diag(H) (the achieved pivoted-Cholesky tolerance). */
+double thx_plan_achieved_tol(const thx_plan *plan, int part);
+
+/* Copy the normalised Cholesky columns of Hankel part `part` to host memory:
+ * ell[r*n + i] = l_r[i] / sqrt(a_r) for r < rank_part, i < n, where n is the
+ * size of that part (n_out receives it; pass ell = NULL to query n only) and
+ * pivots[r] = p_r.  Synchronises `stream`.  For tests and diagnostics. */
+thx_status thx_plan_factors(const thx_plan *plan, int part, double *ell, int32_t *pivots,
+                            int64_t *n_out, hipStream_t stream);
+
+/* One-shot conversions with an internal plan cache keyed by (kind, params,
+ * degree, tol, prec): the first call for a key creates the plan (synchronising
+ * `stream` once), later calls only execute.  Same buffer conventions as
+ * thx_execute with ld = N+1. */
+thx_status thx_leg2cheb(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
+                        thx_precision prec, hipStream_t stream);
+thx_status thx_cheb2leg(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
+                        thx_precision prec, hipStream_t stream);
+thx_status thx_ultra2ultra(const double *alpha, double *beta, int64_t N, int64_t batch,
+                           double lambda1, double lambda2, double tol, thx_precision prec,
+                           hipStream_t stream);
+thx_status thx_lag2lag(const double *alpha, double *beta, int64_t N, int64_t batch, double alpha1,
+                       double alpha2, double tol, thx_precision prec, hipStream_t stream);
+/* Drop every cached plan (synchronises the device). */
+thx_status thx_cache_clear(void);
+
+/* Lambda table (Sec. 1, definition under eq. (M)):
+ * out[i] = Lambda(z0 + i) = Gamma(z0 + i + 1/2) / Gamma(z0 + i + 1), i < count;
+ * out is a device pointer.  Exposed for tests of the generator. */
+thx_status thx_lambda_table(double *out, int64_t count, double z0, hipStream_t stream);
+/* General ratio: out[i] = Gamma(z0 + i + a) / Gamma(z0 + i + b), i < count.
+ * Poles of the numerator return +-inf; poles of the denominator return 0. */
+thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a, double b,
+                                 hipStream_t stream);
+
+const char *thx_status_string(thx_status s);
+int thx_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* THX_H */

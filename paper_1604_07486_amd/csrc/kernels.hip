@@ -1,0 +1,838 @@
+// kernels.hip -- HIP kernels of libthx for gfx950 (MI355X).
+//
+// Fig. 1 of the paper, step by step:
+//   a1  Lambda / Gamma-ratio tables .................. k_gamma_ratio
+//   a2  pivoted Cholesky of the Hankel part(s) ....... k_pchol_init / _select / _column
+//   a3  FFT of the embedded Toeplitz symbol .......... k_symbol_embed + FFT kernels
+//   a4  v = D2 alpha, packed two real halves per complex lane ... k_pack
+//   a5  w = sum_r D_{l_r} T D_{l_r} v via FFTs ....... k_toep_lds / k_mp_p1,p2,p3
+//   a6  beta = D1 w (+ circulant alias term, special row) ...... k_unpack, k_row0
+// plus the O(N^2) direct evaluation used below the FFT crossover (Sec. 4).
+#include "launch.hpp"
+#include "thx_device.hpp"
+#include <math.h>
+
+namespace thx {
+
+// ============================================================================
+// a1: Gamma-ratio generator
+// ============================================================================
+
+__device__ __forceinline__ double gr_series(double w, const GammaRatio &g)
+{
+    const double u = 1.0 / (w * w);
+    double s = g.c[GR_TERMS - 1];
+#pragma unroll
+    for (int j = GR_TERMS - 2; j >= 0; --j) s = fma(s, u, g.c[j]);
+    s *= u;
+    double pw;
+    if (g.pow_mode == -1) pw = 1.0 / sqrt(w);
+    else if (g.pow_mode == 1) pw = sqrt(w);
+    else pw = pow(w, g.amb);
+    return pw * exp(s);
+}
+
+// Gamma(z + a) / Gamma(z + b).  For w = z + (a+b-1)/2 < 12 the argument is
+// raised by k steps: R(z) = R(z+k) prod_{i<k} (z+i+b)/(z+i+a).
+__device__ double gamma_ratio(double z, const GammaRatio &g)
+{
+    const double W0 = 12.0;
+    const double w = z + 0.5 * (g.a + g.b - 1.0);
+    if (w >= W0) return gr_series(w, g);
+    const int k = (int)ceil(W0 - w);
+    double num = 1.0, den = 1.0;
+    for (int i = 0; i < k; ++i) {
+        num *= (z + (double)i + g.b);
+        den *= (z + (double)i + g.a);
+    }
+    if (den == 0.0) return HUGE_VAL; // pole of Gamma(z+a)
+    if (num == 0.0) return 0.0;      // pole of Gamma(z+b)
+    return gr_series(w + (double)k, g) * (num / den);
+}
+
+__global__ void k_gamma_ratio(double *out, int64_t count, double z0, GammaRatio g, double scale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = scale * gamma_ratio(z0 + (double)i, g);
+}
+
+void launch_gamma_ratio(double *out, int64_t count, double z0, const GammaRatio &g, double scale,
+                        hipStream_t s)
+{
+    if (count <= 0) return;
+    const int nt = 256;
+    k_gamma_ratio<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(out, count, z0, g, scale);
+}
+
+// tw[k] = exp(-2 pi i k / M) for k < count, double and (optionally) float
+__global__ void k_twiddles(double *tw64, float *tw32, int64_t M, int64_t count)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    double sn, cs;
+    sincospi(2.0 * (double)k / (double)M, &sn, &cs);
+    tw64[2 * k] = cs;
+    tw64[2 * k + 1] = -sn;
+    if (tw32) {
+        tw32[2 * k] = (float)cs;
+        tw32[2 * k + 1] = (float)(-sn);
+    }
+}
+
+void launch_twiddles(double *tw64, float *tw32, int64_t M, int64_t count, hipStream_t s)
+{
+    const int nt = 256;
+    k_twiddles<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(tw64, tw32, M, count);
+}
+
+__global__ void k_cast(const double *in, float *out, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (float)in[i];
+}
+
+void launch_cast(const double *in, float *out, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return;
+    const int nt = 256;
+    k_cast<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(in, out, count);
+}
+
+__global__ void k_set_value(double *p, double v) { *p = v; }
+void launch_set_value(double *p, double v, hipStream_t s) { k_set_value<<<1, 1, 0, s>>>(p, v); }
+
+// ============================================================================
+// a2: pivoted Cholesky (Sec. 2.1, Fig. 3) of up to two Hankel parts
+// ============================================================================
+//
+// Only the residual diagonal d and the K chosen columns are ever formed.
+// Column r of part q (normalised: l~_r = l_r / sqrt(pivot)) is
+//   l_r[i] = h(i + p_r) - sum_{m<r} l~_m[i] l~_m[p_r],   l~_r = l_r / sqrt(d[p_r]),
+// and d <- d - l~_r^2.  Storage: the normalised columns go to the complex slot
+// array `ell`; for two parts, part q is component q of slot r; for one part,
+// rank r is component (r & 1) of slot r >> 1.
+
+constexpr int PC_NT = 256;
+
+__device__ __forceinline__ int64_t ell_index(int parts, int q, int r, int64_t i, int64_t nc)
+{
+    return parts == 2 ? 2 * ((int64_t)r * nc + i) + q : 2 * ((int64_t)(r >> 1) * nc + i) + (r & 1);
+}
+
+__device__ __forceinline__ void argmax_merge(double &v, int &i, double v2, int i2)
+{
+    if (v2 > v || (v2 == v && i2 < i)) {
+        v = v2;
+        i = i2;
+    }
+}
+
+// block-wide (max, lowest argmax) of (v, i); result valid in thread 0
+__device__ void block_argmax(double &v, int &i, double *sv, int *si)
+{
+    const int t = threadIdx.x;
+    sv[t] = v;
+    si[t] = i;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            double a = sv[t];
+            int ai = si[t];
+            argmax_merge(a, ai, sv[t + h], si[t + h]);
+            sv[t] = a;
+            si[t] = ai;
+        }
+        __syncthreads();
+    }
+    v = sv[0];
+    i = si[0];
+}
+
+__device__ __forceinline__ int64_t hk_offset(const PcholArgs &a, int q)
+{
+    return a.parts == 2 ? q : 0;
+}
+
+__global__ __launch_bounds__(PC_NT) void k_pchol_init(PcholArgs a)
+{
+    __shared__ double sv[PC_NT];
+    __shared__ int si[PC_NT];
+    const int64_t i = (int64_t)blockIdx.x * PC_NT + threadIdx.x;
+    for (int q = 0; q < a.parts; ++q) {
+        double v = 0.0;
+        if (i < a.nc) {
+            if (i >= a.a0[q] && i < a.n[q]) v = a.hk[2 * i + hk_offset(a, q)];
+            a.d[q * a.nc + i] = v;
+        }
+        int idx = (int)i;
+        block_argmax(v, idx, sv, si);
+        if (threadIdx.x == 0) {
+            a.pv[q * a.nblk + blockIdx.x] = v;
+            a.pi[q * a.nblk + blockIdx.x] = idx;
+        }
+        __syncthreads();
+    }
+}
+
+// one block: reduce the partial maxima, apply the stopping rule, publish pivot r
+__global__ __launch_bounds__(1024) void k_pchol_select(PcholArgs a, int r)
+{
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    PcholState *st = a.st;
+    for (int q = 0; q < a.parts; ++q) {
+        if (st->done[q]) {
+            if (threadIdx.x == 0) st->active[q] = 0;
+            continue;
+        }
+        double v = -1.0;
+        int idx = 0x7fffffff;
+        for (int b = threadIdx.x; b < a.nblk; b += blockDim.x)
+            argmax_merge(v, idx, a.pv[q * a.nblk + b], a.pi[q * a.nblk + b]);
+        block_argmax(v, idx, sv, si);
+        __shared__ int go;
+        if (threadIdx.x == 0) {
+            if (r == 0) st->dmax0[q] = v;
+            const double d0 = st->dmax0[q];
+            if (r >= a.kcap || !(v > a.tol * d0) || !(v > 0.0)) {
+                st->done[q] = 1;
+                st->K[q] = r;
+                st->dfinal[q] = d0 > 0.0 ? fmax(v, 0.0) / d0 : 0.0;
+                st->active[q] = 0;
+                go = 0;
+            } else {
+                st->active[q] = 1;
+                st->cur_p[q] = idx;
+                st->cur_piv[q] = v;
+                st->piv[q][r] = idx;
+                go = 1;
+            }
+        }
+        __syncthreads();
+        if (go) {
+            const int p = st->cur_p[q];
+            for (int m = threadIdx.x; m < r; m += blockDim.x)
+                st->R[q][r][m] = a.ell[ell_index(a.parts, q, m, p, a.nc)];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(PC_NT) void k_pchol_column(PcholArgs a, int r)
+{
+    __shared__ double sv[PC_NT];
+    __shared__ int si[PC_NT];
+    const PcholState *st = a.st;
+    const int64_t i = (int64_t)blockIdx.x * PC_NT + threadIdx.x;
+    for (int q = 0; q < a.parts; ++q) {
+        if (!st->active[q]) continue; // uniform across the grid
+        const int p = st->cur_p[q];
+        const double sq = sqrt(st->cur_piv[q]);
+        double dn = 0.0;
+        if (i < a.nc) {
+            dn = a.d[q * a.nc + i];
+            if (i >= a.a0[q] && i < a.n[q]) {
+                double acc = a.hk[i + p + hk_offset(a, q)];
+                const double *Rr = st->R[q][r];
+                for (int m = 0; m < r; ++m) acc = fma(-a.ell[ell_index(a.parts, q, m, i, a.nc)], Rr[m], acc);
+                const double lt = acc / sq;
+                a.ell[ell_index(a.parts, q, r, i, a.nc)] = lt;
+                dn = fma(-lt, lt, dn);
+                if (!(dn > 0.0) || i == p) dn = 0.0;
+                a.d[q * a.nc + i] = dn;
+            }
+        }
+        int idx = (int)i;
+        block_argmax(dn, idx, sv, si);
+        if (threadIdx.x == 0) {
+            a.pv[q * a.nblk + blockIdx.x] = dn;
+            a.pi[q * a.nblk + blockIdx.x] = idx;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_pchol_init(const PcholArgs &a, hipStream_t s)
+{
+    k_pchol_init<<<a.nblk, PC_NT, 0, s>>>(a);
+}
+
+void launch_pchol_step(const PcholArgs &a, int r, hipStream_t s)
+{
+    k_pchol_select<<<1, 1024, 0, s>>>(a, r);
+    k_pchol_column<<<a.nblk, PC_NT, 0, s>>>(a, r);
+}
+
+// ============================================================================
+// a3: Toeplitz symbol as the first column of a circulant
+// ============================================================================
+// y_a = sum_{b >= a} t_{b-a} z_b is the circular correlation with
+// e[0] = t_0, e[L-m] = t_m (0 < m < nt), zero elsewhere; then
+// y = IFFT(FFT(z) . FFT(e)) restricted to a < n.
+__global__ void k_symbol_embed(const double *t, int64_t nt, double *emb, int64_t L)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    double v = 0.0;
+    if (i == 0) v = t[0];
+    else if (L - i < nt) v = t[L - i];
+    emb[2 * i] = v;
+    emb[2 * i + 1] = 0.0;
+}
+
+void launch_symbol_embed(const double *t, int64_t nt, double *emb, int64_t L, hipStream_t s)
+{
+    const int nt_ = 256;
+    k_symbol_embed<<<(unsigned)((L + nt_ - 1) / nt_), nt_, 0, s>>>(t, nt, emb, L);
+}
+
+// Reorder a double-precision spectrum (complex, length L) into the working
+// precision.  mode 0: same order; mode 1: from the three-pass order
+// in[k2 L1 + k1] to natural order out[k2 + L2 k1]; mode 2: natural order to
+// the three-pass order out[k2 L1 + k1] = in[k2 + L2 k1].
+template <typename T>
+__global__ void k_reorder(const double *in, cpx<T> *out, int64_t L, int64_t L1, int64_t L2, int mode)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    int64_t src = i;
+    if (mode == 1) src = (i % L2) * L1 + i / L2;
+    else if (mode == 2) src = (i / L1) + L2 * (i % L1);
+    out[i] = cpx<T>{(T)in[2 * src], (T)in[2 * src + 1]};
+}
+
+template <typename T>
+void launch_reorder(const double *in, void *out, int64_t L, int64_t L1, int64_t L2, int mode, hipStream_t s)
+{
+    const int nt = 256;
+    k_reorder<T><<<(unsigned)((L + nt - 1) / nt), nt, 0, s>>>(in, (cpx<T> *)out, L, L1, L2, mode);
+}
+template void launch_reorder<double>(const double *, void *, int64_t, int64_t, int64_t, int, hipStream_t);
+template void launch_reorder<float>(const double *, void *, int64_t, int64_t, int64_t, int, hipStream_t);
+
+// ============================================================================
+// Diagonal factors
+// ============================================================================
+
+__device__ __forceinline__ double d1_of(const KindDesc &k, int64_t j)
+{
+    if (k.d1tab) return k.d1tab[j];
+    switch (k.kind) {
+    case 0: return j == 0 ? M_1_PI : M_2_PI;           // leg2cheb: (2/pi) diag(1/2, 1, ...)
+    case 1: return (double)j + 0.5;                    // cheb2leg: diag(j + 1/2)
+    case 2: return (double)j + k.p[1];                 // ultra: diag(j + lambda2)
+    default: return 1.0;
+    }
+}
+
+__device__ __forceinline__ double d2_of(const KindDesc &k, int64_t j)
+{
+    if (k.d2tab) return k.d2tab[j];
+    if (k.kind == 1) return j == 0 ? -0.5641895835477562869480795 /* -1/sqrt(pi) */ : -0.25 * (double)j;
+    return 1.0;
+}
+
+// ============================================================================
+// a4: pack v = D2 alpha into complex lanes
+// ============================================================================
+// parity-split kinds: lane a holds (v_{2a}, v_{2a+1}); otherwise (v_a, v_a).
+template <typename T>
+__global__ void k_pack(KindDesc k, const double *alpha, int64_t ld, int64_t N, cpx<T> *X, int64_t nc)
+{
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (a >= nc) return;
+    const double *al = alpha + b * ld;
+    double x = 0.0, y = 0.0;
+    if (k.parity) {
+        const int64_t j0 = 2 * a, j1 = 2 * a + 1;
+        if (j0 <= N) x = d2_of(k, j0) * al[j0];
+        if (j1 <= N) y = d2_of(k, j1) * al[j1];
+    } else if (a <= N) {
+        x = y = d2_of(k, a) * al[a];
+    }
+    X[b * nc + a] = cpx<T>{(T)x, (T)y};
+}
+
+template <typename T>
+void launch_pack(const KindDesc &k, const double *alpha, int64_t ld, int64_t N, int64_t batch,
+                 void *X, int64_t nc, hipStream_t s)
+{
+    const int nt = 256;
+    dim3 grid((unsigned)((nc + nt - 1) / nt), (unsigned)batch);
+    k_pack<T><<<grid, nt, 0, s>>>(k, alpha, ld, N, (cpx<T> *)X, nc);
+}
+template void launch_pack<double>(const KindDesc &, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
+template void launch_pack<float>(const KindDesc &, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
+
+// ============================================================================
+// a6: sum the partial results, remove the circulant alias, beta = D1 w
+// ============================================================================
+// When L = 2n - 2 for a half of size n, the correlation picks up exactly one
+// extra term t_{n-1} z_0 at output n-1; it is removed here in double precision:
+//   w_{n-1} -= t_{n-1} v_0 sum_s l~_s[n-1] l~_s[0].
+template <typename T>
+__global__ void k_unpack(KindDesc k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                         const cpx<T> *W, int G, int64_t nc, int64_t batch, int64_t L,
+                         const double *ell64, int64_t nc_ell, int S, const double *tsym,
+                         const double *row0)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (j > N) return;
+    const double *al = alpha + b * ld;
+    double w = 0.0;
+    if (k.parity) {
+        const int64_t a = j >> 1;
+        const int q = (int)(j & 1);
+        for (int g = 0; g < G; ++g) {
+            const cpx<T> v = W[((int64_t)g * batch + b) * nc + a];
+            w += q ? (double)v.y : (double)v.x;
+        }
+        const int64_t nq = q ? (N + 1) / 2 : N / 2 + 1;
+        if (2 * nq - 2 == L && a == nq - 1) {
+            double gs = 0.0;
+            for (int s = 0; s < S; ++s)
+                gs = fma(ell64[2 * ((int64_t)s * nc_ell + nq - 1) + q], ell64[2 * ((int64_t)s * nc_ell) + q], gs);
+            w -= tsym[nq - 1] * gs * (d2_of(k, q) * al[q]);
+        }
+    } else {
+        for (int g = 0; g < G; ++g) {
+            const cpx<T> v = W[((int64_t)g * batch + b) * nc + j];
+            w += (double)v.x + (double)v.y;
+        }
+        const int64_t n = N + 1;
+        if (2 * n - 2 == L && j == n - 1) {
+            double gs = 0.0;
+            for (int s = 0; s < S; ++s) {
+                const int64_t e = 2 * ((int64_t)s * nc_ell + n - 1), o = 2 * ((int64_t)s * nc_ell);
+                gs = fma(ell64[e], ell64[o], gs);
+                gs = fma(ell64[e + 1], ell64[o + 1], gs);
+            }
+            w -= tsym[n - 1] * gs * (d2_of(k, 0) * al[0]);
+        }
+    }
+    double out = d1_of(k, j) * w;
+    if (row0 && j == 0) out = row0[b];
+    beta[b * ld + j] = out;
+}
+
+template <typename T>
+void launch_unpack(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                   int64_t batch, const void *Wpart, int G, int64_t nc, int64_t L,
+                   const double *ell64, int64_t nc_ell, int S, const double *tsym,
+                   const double *row0, hipStream_t s)
+{
+    const int nt = 256;
+    dim3 grid((unsigned)((N + 1 + nt - 1) / nt), (unsigned)batch);
+    k_unpack<T><<<grid, nt, 0, s>>>(k, alpha, ld, beta, N, (const cpx<T> *)Wpart, G, nc, batch, L,
+                                    ell64, nc_ell, S, tsym, row0);
+}
+template void launch_unpack<double>(const KindDesc &, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
+template void launch_unpack<float>(const KindDesc &, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
+
+// Row 0 of cheb2leg computed directly (Sec. 5.1): the Hankel part is not PSD
+// because of H_00, so rows/columns >= 1 go through the low-rank path and
+//   beta_0 = D1_0 sum_{b >= 0} t_b h(b) D2_{2b} alpha_{2b},  h(0) := 1.
+__global__ __launch_bounds__(256) void k_row0(KindDesc k, const double *alpha, int64_t ld, int64_t N,
+                                              const double *tsym, const double *hk, double *row0)
+{
+    __shared__ double sm[256];
+    const int64_t b = blockIdx.x;
+    const double *al = alpha + b * ld;
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; 2 * c <= N; c += blockDim.x)
+        acc = fma(tsym[c] * hk[c], d2_of(k, 2 * c) * al[2 * c], acc);
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row0[b] = d1_of(k, 0) * sm[0];
+}
+
+void launch_row0_cheb2leg(const KindDesc &k, const double *alpha, int64_t ld, int64_t N,
+                          int64_t batch, const double *tsym, const double *hk, double *row0,
+                          hipStream_t s)
+{
+    k_row0<<<(unsigned)batch, 256, 0, s>>>(k, alpha, ld, N, tsym, hk, row0);
+}
+
+// ============================================================================
+// Direct O(N^2) evaluation (Sec. 4 "Direct"): entries generated on the fly
+// ============================================================================
+__global__ void k_direct(KindDesc k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                         const double *tsym, const double *hk)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = blockIdx.y;
+    if (j > N) return;
+    const double *al = alpha + b * ld;
+    double acc = 0.0;
+    if (k.parity) {
+        for (int64_t c = j; c <= N; c += 2)
+            acc = fma(tsym[(c - j) >> 1] * hk[(j + c) >> 1], d2_of(k, c) * al[c], acc);
+    } else {
+        for (int64_t c = j; c <= N; ++c) acc = fma(tsym[c - j] * hk[j + c], d2_of(k, c) * al[c], acc);
+    }
+    beta[b * ld + j] = d1_of(k, j) * acc;
+}
+
+void launch_direct(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                   int64_t batch, const double *tsym, const double *hk, hipStream_t s)
+{
+    const int nt = 128;
+    dim3 grid((unsigned)((N + 1 + nt - 1) / nt), (unsigned)batch);
+    k_direct<<<grid, nt, 0, s>>>(k, alpha, ld, beta, N, tsym, hk);
+}
+
+// ============================================================================
+// a5: sums of diagonally scaled Toeplitz products, eq. (Cdecomposition)
+// ============================================================================
+
+template <int L>
+constexpr int lds_threads() { return L / 4 < 64 ? 64 : (L / 4 > 256 ? 256 : L / 4); }
+
+// One workgroup per (slot group, vector): for each slot s of the group
+//   z = l~_s o X (zero-padded to L) -> FFT -> . that -> IFFT -> acc += l~_s o y
+// with `that` = FFT(symbol)/L.  The accumulator stays in registers.
+template <typename T, int L>
+__global__ __launch_bounds__(lds_threads<L>()) void k_toep_lds(
+    const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int S,
+    int spg, const cpx<T> *__restrict__ that, const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ W,
+    int64_t batch)
+{
+    constexpr int NT = lds_threads<L>();
+    constexpr int E = L / NT;
+    __shared__ cpx<T> buf[L];
+    const int g = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    const int s0 = g * spg;
+    const int s1 = min(S, s0 + spg);
+    const int tid = threadIdx.x;
+    cpx<T> acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
+    const cpx<T> *Xb = X + b * nc;
+    for (int s = s0; s < s1; ++s) {
+        const cpx<T> *es = ell + (int64_t)s * nc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = tid + e * NT;
+            cpx<T> z = {0, 0};
+            if (i < n) z = cdiag(es[i], Xb[i]);
+            buf[i] = z;
+        }
+        __syncthreads();
+        lds_fft<T, L, 1, NT, false>(buf, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = tid + e * NT;
+            buf[i] = cmul(buf[i], that[i]);
+        }
+        __syncthreads();
+        lds_fft<T, L, 1, NT, true>(buf, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = tid + e * NT;
+            if (i < n) acc[e] = cadd(acc[e], cdiag(es[i], buf[i]));
+        }
+        __syncthreads();
+    }
+    cpx<T> *Wg = W + ((int64_t)g * batch + b) * nc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = tid + e * NT;
+        if (i < n) Wg[i] = acc[e];
+    }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(lds_threads<L>()) void k_fft_lds(const cpx<T> *in, cpx<T> *out,
+                                                             const cpx<T> *tw, T scale)
+{
+    constexpr int NT = lds_threads<L>();
+    __shared__ cpx<T> buf[L];
+    for (int i = threadIdx.x; i < L; i += NT) buf[i] = in[i];
+    __syncthreads();
+    lds_fft<T, L, 1, NT, false>(buf, tw);
+    for (int i = threadIdx.x; i < L; i += NT) out[i] = cpx<T>{buf[i].x * scale, buf[i].y * scale};
+}
+
+template <typename T, int L>
+static void run_toep_lds(const void *X, int64_t nc, int64_t n, const void *ell, int S, int spg, int G,
+                         const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
+{
+    dim3 grid((unsigned)G, (unsigned)batch);
+    k_toep_lds<T, L><<<grid, lds_threads<L>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
+                                                      S, spg, (const cpx<T> *)that,
+                                                      (const cpx<T> *)tw, (cpx<T> *)W, batch);
+}
+
+template <typename T>
+bool launch_toep_lds(int64_t L, const void *X, int64_t nc, int64_t n, const void *ell, int S,
+                     int spg, int G, const void *that, const void *tw, void *W, int64_t batch,
+                     hipStream_t s)
+{
+    switch (L) {
+#define THX_CASE(LL) case LL: run_toep_lds<T, LL>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s); return true;
+        THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
+        THX_CASE(4096)
+#undef THX_CASE
+    case 8192:
+        if constexpr (sizeof(T) == 4) {
+            run_toep_lds<T, 8192>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
+            return true;
+        }
+        return false;
+    default: return false;
+    }
+}
+template bool launch_toep_lds<double>(int64_t, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
+template bool launch_toep_lds<float>(int64_t, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
+
+template <typename T>
+bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale, hipStream_t s)
+{
+    switch (L) {
+#define THX_CASE(LL) case LL: k_fft_lds<T, LL><<<1, lds_threads<LL>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out, (const cpx<T> *)tw, (T)scale); return true;
+        THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
+        THX_CASE(4096)
+#undef THX_CASE
+    case 8192:
+        if constexpr (sizeof(T) == 4) {
+            k_fft_lds<T, 8192><<<1, lds_threads<8192>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out,
+                                                                (const cpx<T> *)tw, (T)scale);
+            return true;
+        }
+        return false;
+    default: return false;
+    }
+}
+template bool launch_fft_lds<double>(int64_t, const void *, void *, const void *, double, hipStream_t);
+template bool launch_fft_lds<float>(int64_t, const void *, void *, const void *, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Three-pass (four-step) FFT for L = L1 * L2 > one workgroup's LDS.
+// Index a = a1 + L1 a2 (a1 < L1 fast), frequency k = k2 + L2 k1.
+//   P1: column DFTs over a2 (length L2) for TC adjacent columns, twiddle
+//       w_L^{a1 k2}, result at position a1 + L1 k2;
+//   P2: each row k2 (contiguous, length L1): DFT over a1 gives Z[k2 + L2 k1];
+//       multiply by the symbol stored in the same permuted order, inverse DFT,
+//       conjugate twiddle w_L^{-a1 k2};
+//   P3: inverse column DFTs over k2 give y[a1 + L1 a2] in natural order, which
+//       is scaled by l~_s and summed over the slots of the group.
+// ---------------------------------------------------------------------------
+template <typename T> constexpr int mp_tile() { return sizeof(T) == 8 ? 4096 : 8192; }
+template <typename T, int L2> constexpr int mp_tc() { return mp_tile<T>() / L2 > 64 ? 64 : mp_tile<T>() / L2; }
+template <typename T, int L2> constexpr int mp_nt()
+{
+    return mp_tc<T, L2>() * L2 / 4 < 64 ? 64 : (mp_tc<T, L2>() * L2 / 4 > 256 ? 256 : mp_tc<T, L2>() * L2 / 4);
+}
+
+template <typename T>
+MultiPassGeom multipass_geom(int64_t L)
+{
+    MultiPassGeom g;
+    g.L = L;
+    g.L1 = lds_max_len<T>();
+    g.L2 = L / g.L1;
+    const int64_t tc = mp_tile<T>() / g.L2;
+    g.TC = tc > 64 ? 64 : tc;
+    return g;
+}
+template MultiPassGeom multipass_geom<double>(int64_t);
+template MultiPassGeom multipass_geom<float>(int64_t);
+
+template <typename T, int L2>
+__global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
+    const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
+    const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
+    const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA)
+{
+    constexpr int TC = mp_tc<T, L2>(), NT = mp_nt<T, L2>();
+    constexpr int L1 = (int)lds_max_len<T>();
+    constexpr int64_t L = (int64_t)L1 * L2;
+    __shared__ cpx<T> buf[L2 * TC];
+    const int a1_0 = blockIdx.x * TC;
+    const int sl = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const cpx<T> *es = ell ? ell + (int64_t)(slot0 + sl) * nc : nullptr;
+    const cpx<T> *Xb = X ? X + b * nc : nullptr;
+    for (int idx = threadIdx.x; idx < L2 * TC; idx += NT) {
+        const int a2 = idx / TC, c = idx % TC;
+        const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+        cpx<T> z = {0, 0};
+        if (es) {
+            if (a < n) z = cdiag(es[a], Xb[a]);
+        } else {
+            z = src[a];
+        }
+        buf[idx] = z;
+    }
+    __syncthreads();
+    lds_fft<T, L2, TC, NT, false>(buf, twL2);
+    cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
+    for (int idx = threadIdx.x; idx < L2 * TC; idx += NT) {
+        const int k2 = idx / TC, c = idx % TC;
+        const int a1 = a1_0 + c;
+        const int64_t e = (int64_t)a1 * k2; // < L
+        const cpx<T> t = cmul(twA[e % L1], twL2[e / L1]);
+        Ub[a1 + (int64_t)L1 * k2] = cmul(buf[idx], t);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mp_p2(cpx<T> *U, int L2, const cpx<T> *__restrict__ that_perm,
+                                               const cpx<T> *__restrict__ twL1,
+                                               const cpx<T> *__restrict__ twA,
+                                               const cpx<T> *__restrict__ twL2, int full,
+                                               cpx<T> *__restrict__ out, T scale)
+{
+    constexpr int L1 = (int)lds_max_len<T>();
+    constexpr int NT = 256, E = L1 / NT;
+    __shared__ cpx<T> buf[L1];
+    const int k2 = blockIdx.x;
+    const int64_t L = (int64_t)L1 * L2;
+    cpx<T> *row = U + (int64_t)blockIdx.y * L + (int64_t)k2 * L1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) buf[threadIdx.x + e * NT] = row[threadIdx.x + e * NT];
+    __syncthreads();
+    lds_fft<T, L1, 1, NT, false>(buf, twL1);
+    if (!full) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = threadIdx.x + e * NT;
+            out[(int64_t)k2 * L1 + i] = cpx<T>{buf[i].x * scale, buf[i].y * scale};
+        }
+        return;
+    }
+    const cpx<T> *tp = that_perm + (int64_t)k2 * L1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = threadIdx.x + e * NT;
+        buf[i] = cmul(buf[i], tp[i]);
+    }
+    __syncthreads();
+    lds_fft<T, L1, 1, NT, true>(buf, twL1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int a1 = threadIdx.x + e * NT;
+        const int64_t ex = (int64_t)a1 * k2;
+        const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
+        row[a1] = cmulc(buf[a1], t);
+    }
+}
+
+template <typename T, int L2>
+__global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
+    const cpx<T> *__restrict__ U, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
+    int nslots, int spg, cpx<T> *__restrict__ W, int gofs, int64_t batch,
+    const cpx<T> *__restrict__ twL2)
+{
+    constexpr int TC = mp_tc<T, L2>(), NT = mp_nt<T, L2>();
+    constexpr int L1 = (int)lds_max_len<T>();
+    constexpr int64_t L = (int64_t)L1 * L2;
+    constexpr int E = L2 * TC / NT;
+    __shared__ cpx<T> buf[L2 * TC];
+    const int a1_0 = blockIdx.x * TC;
+    const int g = blockIdx.y;
+    const int64_t b = blockIdx.z;
+    const int tid = threadIdx.x;
+    cpx<T> acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
+    const int s1 = min(nslots, (g + 1) * spg);
+    for (int sl = g * spg; sl < s1; ++sl) {
+        const cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * NT;
+            const int k2 = idx / TC, c = idx % TC;
+            buf[idx] = Ub[a1_0 + c + (int64_t)L1 * k2];
+        }
+        __syncthreads();
+        lds_fft<T, L2, TC, NT, true>(buf, twL2);
+        const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int idx = tid + e * NT;
+            const int a2 = idx / TC, c = idx % TC;
+            const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+            if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], buf[idx]));
+        }
+        __syncthreads();
+    }
+    cpx<T> *Wg = W + ((int64_t)(gofs + g) * batch + b) * nc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int idx = tid + e * NT;
+        const int a2 = idx / TC, c = idx % TC;
+        const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+        if (a < n) Wg[a] = acc[e];
+    }
+}
+
+#define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename T>
+bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
+                  int slot0, int nslots, const void *src, void *U, int64_t batch, const void *twL2,
+                  const void *twA, hipStream_t s)
+{
+    switch (g.L2) {
+#define THX_P1(LL2)                                                                                   \
+    case LL2:                                                                                         \
+        if (LL2 * (int64_t)lds_max_len<T>() > (int64_t)1 << 22) return false;                         \
+        k_mp_p1<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>()), (unsigned)nslots, (unsigned)batch), \
+                          mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,     \
+                                                   slot0, (const cpx<T> *)src, (cpx<T> *)U, batch,    \
+                                                   (const cpx<T> *)twL2, (const cpx<T> *)twA);        \
+        return true;
+        THX_L2_CASES(THX_P1)
+#undef THX_P1
+    default: return false;
+    }
+}
+template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+
+template <typename T>
+bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,
+                  const void *twL1, const void *twA, const void *twL2, bool full, void *out,
+                  double scale, hipStream_t s)
+{
+    if (g.L1 != lds_max_len<T>() || g.L2 < 2 || g.L2 > 1024) return false;
+    dim3 grid((unsigned)g.L2, (unsigned)(nslots * batch));
+    k_mp_p2<T><<<grid, 256, 0, s>>>((cpx<T> *)U, (int)g.L2, (const cpx<T> *)that_perm,
+                                    (const cpx<T> *)twL1, (const cpx<T> *)twA,
+                                    (const cpx<T> *)twL2, full ? 1 : 0, (cpx<T> *)out, (T)scale);
+    return true;
+}
+template bool launch_mp_p2<double>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
+template bool launch_mp_p2<float>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
+
+template <typename T>
+bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell,
+                  int slot0, int nslots, int spg, int G, void *Wpart, int gofs, int64_t batch,
+                  const void *twL2, hipStream_t s)
+{
+    switch (g.L2) {
+#define THX_P3(LL2)                                                                                   \
+    case LL2:                                                                                         \
+        if (LL2 * (int64_t)lds_max_len<T>() > (int64_t)1 << 22) return false;                         \
+        k_mp_p3<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>()), (unsigned)G, (unsigned)batch),     \
+                          mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)U, nc, n, (const cpx<T> *)ell,     \
+                                                   slot0, nslots, spg, (cpx<T> *)Wpart, gofs, batch,  \
+                                                   (const cpx<T> *)twL2);                             \
+        return true;
+        THX_L2_CASES(THX_P3)
+#undef THX_P3
+    default: return false;
+    }
+}
+template bool launch_mp_p3<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, int, void *, int, int64_t, const void *, hipStream_t);
+template bool launch_mp_p3<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, int, void *, int, int64_t, const void *, hipStream_t);
+
+} // namespace thx

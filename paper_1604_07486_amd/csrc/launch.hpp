@@ -1,0 +1,141 @@
+// launch.hpp -- host-side launchers of the libthx kernels (kernels.hip) and the
+// small POD descriptors they take.  Everything here is internal to libthx.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace thx {
+
+// Asymptotic series of log(Gamma(z+a)/Gamma(z+b)) in w = z + (a+b-1)/2:
+//   (a-b) log w + sum_{j>=1} c_j w^{-2j},  c_j = -B_{2j+1}((1+a-b)/2) / (j(2j+1)),
+// where B_n is the Bernoulli polynomial (the odd powers of 1/w vanish with this
+// shift).  Used for w >= 12; smaller arguments are shifted up with
+// Gamma(x+1) = x Gamma(x).
+constexpr int GR_TERMS = 10;
+struct GammaRatio {
+    double a, b, amb;
+    double c[GR_TERMS];
+    int pow_mode; // -1: w^{-1/2}, +1: w^{1/2}, 0: pow(w, a-b)
+};
+GammaRatio make_gamma_ratio(double a, double b);
+
+// Diagonal factors D1, D2 of A = D1 (T o H) D2 for the kinds whose diagonals
+// have a short closed form (the others pass tables).
+struct KindDesc {
+    int kind;     // thx_kind
+    int parity;   // 1: A_jk = 0 for odd k - j (split into even/odd halves)
+    double p[4];  // kind parameters
+    const double *d1tab; // optional D1 table (length >= N+1), else closed form
+    const double *d2tab; // optional D2 table
+};
+
+// Device state of the pivoted Cholesky (two independent parts at most).
+constexpr int KMAX = 128;
+struct PcholState {
+    int K[2];
+    int done[2];
+    int active[2];
+    int cur_p[2];
+    double cur_piv[2];
+    double dmax0[2];
+    double dfinal[2];
+    int piv[2][KMAX];
+    double R[2][KMAX][KMAX]; // R[q][r][i] = normalised column i of part q at pivot p_r
+};
+
+// ---- a1: tables --------------------------------------------------------------
+void launch_gamma_ratio(double *out, int64_t count, double z0, const GammaRatio &g, double scale,
+                        hipStream_t s);
+// tw[k] = exp(-2 pi i k / M), k < count
+void launch_twiddles(double *tw64, float *tw32, int64_t M, int64_t count, hipStream_t s);
+void launch_cast(const double *in, float *out, int64_t count, hipStream_t s);
+void launch_set_value(double *p, double v, hipStream_t s);
+
+// ---- a2: pivoted Cholesky ------------------------------------------------------
+// parts: 2 for parity-split kinds (even/odd, generator h_q(s) = hk[s + q]),
+// 1 otherwise (generator hk[s]).  n[q]: part sizes; a0[q]: first index taking
+// part (rows below are excluded).  ell: [KMAX slots][nc] complex doubles.
+struct PcholArgs {
+    const double *hk;
+    double *d;        // residual diagonals [parts][nc]
+    double *ell;      // (double*) of the complex [slot][nc] array
+    int64_t nc;
+    int64_t n[2];
+    int64_t a0[2];
+    int parts;
+    double tol;
+    int kcap;
+    PcholState *st;
+    double *pv;       // block partial maxima [parts][nblk]
+    int *pi;          // block partial argmax [parts][nblk]
+    int nblk;
+};
+void launch_pchol_init(const PcholArgs &a, hipStream_t s);
+void launch_pchol_step(const PcholArgs &a, int r, hipStream_t s);
+
+// ---- a3: Toeplitz symbol -------------------------------------------------------
+// embed t_m (m < nt) as the first column of the circulant of length L that
+// realises the upper-triangular Toeplitz product as a circular correlation.
+void launch_symbol_embed(const double *t, int64_t nt, double *emb /*complex L*/, int64_t L,
+                         hipStream_t s);
+
+// reorder a double spectrum into working precision T: mode 0 same order, 1 three-pass
+// order (L1, L2) -> natural, 2 natural -> three-pass order (L1, L2)
+template <typename T>
+void launch_reorder(const double *in, void *out, int64_t L, int64_t L1, int64_t L2, int mode,
+                    hipStream_t s);
+
+// ---- a4 / a6: pack and unpack ----------------------------------------------------
+template <typename T>
+void launch_pack(const KindDesc &k, const double *alpha, int64_t ld, int64_t N, int64_t batch,
+                 void *X /*cpx<T> [batch][nc]*/, int64_t nc, hipStream_t s);
+template <typename T>
+void launch_unpack(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                   int64_t batch, const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc,
+                   int64_t L, const double *ell64, int64_t nc_ell, int S, const double *tsym,
+                   const double *row0, hipStream_t s);
+void launch_row0_cheb2leg(const KindDesc &k, const double *alpha, int64_t ld, int64_t N,
+                          int64_t batch, const double *tsym, const double *hk, double *row0,
+                          hipStream_t s);
+
+// ---- direct O(N^2) ----------------------------------------------------------------
+void launch_direct(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
+                   int64_t batch, const double *tsym, const double *hk, hipStream_t s);
+
+// ---- a5: Toeplitz products ---------------------------------------------------------
+// Largest length handled by one workgroup in LDS, and the row length of the
+// three-pass scheme (same value).
+template <typename T> constexpr int64_t lds_max_len() { return sizeof(T) == 8 ? 4096 : 8192; }
+
+// single-workgroup path: W[g] = sum_{s in group g} ell_s o IFFT(FFT(ell_s o X) . that)
+template <typename T>
+bool launch_toep_lds(int64_t L, const void *X, int64_t nc, int64_t n, const void *ell, int S,
+                     int slots_per_group, int G, const void *that, const void *tw, void *Wpart,
+                     int64_t batch, hipStream_t s);
+// plain forward FFT of one length-L complex array in LDS (symbol transform), scaled
+template <typename T>
+bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale,
+                    hipStream_t s);
+
+struct MultiPassGeom {
+    int64_t L, L1, L2, TC;
+};
+template <typename T> MultiPassGeom multipass_geom(int64_t L);
+// P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr)
+template <typename T>
+bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
+                  int slot0, int nslots, const void *src, void *U, int64_t batch,
+                  const void *twL2, const void *twA, hipStream_t s);
+// P2: row FFT, times permuted symbol, inverse row FFT, conjugate twiddle (full);
+// or forward row FFT only, scaled, written to `out` (symbol transform)
+template <typename T>
+bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,
+                  const void *twL1, const void *twA, const void *twL2, bool full, void *out,
+                  double scale, hipStream_t s);
+// P3: inverse column FFTs, scaled by ell_s and summed over the slots of group g
+template <typename T>
+bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell,
+                  int slot0, int nslots, int slots_per_group, int G, void *Wpart, int gofs,
+                  int64_t batch, const void *twL2, hipStream_t s);
+
+} // namespace thx

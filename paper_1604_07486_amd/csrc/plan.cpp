@@ -1,0 +1,740 @@
+// plan.cpp -- host side of libthx: plans (Fig. 1 steps 1-2 plus the symbol
+// FFT), execution (steps 3-5), a plan cache for the one-shot calls, and the
+// C ABI declared in include/thx.h.  All arithmetic of the conversion runs in
+// the kernels of kernels.hip; the host only sizes buffers, computes the
+// dozen series coefficients of the Gamma-ratio generator, and launches.
+#include "../../include/thx.h"
+#include "launch.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+using namespace thx;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+struct HipFail {
+    hipError_t e;
+};
+
+inline void hip_check(hipError_t e)
+{
+    if (e != hipSuccess) throw HipFail{e};
+}
+inline void launch_check() { hip_check(hipGetLastError()); }
+
+template <typename T>
+T *dalloc(int64_t count)
+{
+    void *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    hip_check(e);
+    return (T *)p;
+}
+inline void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+int64_t next_pow2(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// Gamma-ratio series coefficients: c_j = -B_{2j+1}(x) / (j (2j+1)),
+// x = (1 + a - b)/2, with the Bernoulli polynomial B_n(x) = sum_k C(n,k) B_k x^{n-k}.
+// ---------------------------------------------------------------------------
+GammaRatio thx::make_gamma_ratio(double a, double b)
+{
+    static const long double Bn[21] = {1.0L, -0.5L, 1.0L / 6, 0, -1.0L / 30, 0, 1.0L / 42, 0,
+                                       -1.0L / 30, 0, 5.0L / 66, 0, -691.0L / 2730, 0, 7.0L / 6, 0,
+                                       -3617.0L / 510, 0, 43867.0L / 798, 0, -174611.0L / 330};
+    GammaRatio g;
+    g.a = a;
+    g.b = b;
+    g.amb = a - b;
+    g.pow_mode = (a - b == -0.5) ? -1 : ((a - b == 0.5) ? 1 : 0);
+    const long double x = (1.0L + (long double)a - (long double)b) / 2;
+    for (int j = 1; j <= GR_TERMS; ++j) {
+        const int n = 2 * j + 1;
+        long double bp = 0, binom = 1; // C(n, k)
+        for (int k = 0; k <= n; ++k) {
+            if (k > 0) binom = binom * (long double)(n - k + 1) / (long double)k;
+            if (k <= 20 && Bn[k] != 0) bp += binom * Bn[k] * powl(x, (long double)(n - k));
+        }
+        g.c[j - 1] = (double)(-bp / ((long double)j * (long double)n));
+    }
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct thx_plan {
+    thx_kind kind = THX_LEG2CHEB;
+    double params[4] = {0, 0, 0, 0};
+    int64_t N = 0;
+    double tol = 0;
+    thx_precision prec = THX_FP64;
+    uint32_t flags = 0;
+    KindDesc kd{};
+    int path = 0;   // 0 direct, 1 LDS, 2 three-pass
+    int64_t nc = 0; // complex lanes
+    int parts = 0;
+    int64_t npart[2] = {0, 0}, a0[2] = {0, 0};
+    int64_t L = 0;
+    MultiPassGeom geom{};
+    int K[2] = {-1, -1};
+    double dfinal[2] = {0, 0};
+    int S = 0;            // complex FFT slots
+    int slots_alloc = 0;  // allocated slots in ell64
+    bool tol_reached = true;
+    // device tables
+    double *tsym = nullptr;
+    double *hk = nullptr;
+    bool tsym_alias = false;
+    double *d1tab = nullptr, *d2tab = nullptr;
+    double *ell64 = nullptr;
+    float *ell32 = nullptr;
+    void *that = nullptr;     // symbol spectrum in working precision (natural or permuted)
+    void *twL = nullptr;      // LDS path: w_L^k, k < L
+    void *twL1 = nullptr, *twL2 = nullptr, *twA = nullptr; // three-pass tables
+    double *tw64_keep[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t *pivots[2] = {nullptr, nullptr}; // host copies
+    // workspace (grown on demand; executions of one plan must be serialised)
+    int64_t ws_batch = 0;
+    void *X = nullptr, *Wp = nullptr, *U = nullptr;
+    double *row0 = nullptr;
+    int64_t U_slots = 0;
+    int Gmax = 0;
+
+    size_t esize() const { return prec == THX_FP64 ? 16 : 8; }
+    ~thx_plan()
+    {
+        dfree(tsym_alias ? nullptr : tsym);
+        dfree(hk);
+        dfree(d1tab);
+        dfree(d2tab);
+        dfree(ell64);
+        dfree(ell32);
+        dfree(that);
+        if (prec == THX_FP64) {
+            dfree(twL);
+            dfree(twL1);
+            dfree(twL2);
+            dfree(twA);
+        } else {
+            dfree(twL);
+            dfree(twL1);
+            dfree(twL2);
+            dfree(twA);
+            for (double *p : tw64_keep) dfree(p);
+        }
+        dfree(X);
+        dfree(Wp);
+        dfree(U);
+        dfree(row0);
+        delete[] pivots[0];
+        delete[] pivots[1];
+    }
+};
+
+namespace {
+
+int64_t direct_crossover()
+{
+    static int64_t v = [] {
+        const char *e = getenv("THX_DIRECT_MAX");
+        return e ? (int64_t)atoll(e) : (int64_t)512;
+    }();
+    return v;
+}
+
+// Twiddle table w_M^k (k < count) in the plan's working precision.
+void *make_twiddles(thx_plan *p, int64_t M, int64_t count, hipStream_t s, int keep_slot)
+{
+    double *t64 = dalloc<double>(2 * count);
+    if (p->prec == THX_FP64) {
+        launch_twiddles(t64, nullptr, M, count, s);
+        launch_check();
+        return t64;
+    }
+    float *t32 = dalloc<float>(2 * count);
+    launch_twiddles(t64, t32, M, count, s);
+    launch_check();
+    p->tw64_keep[keep_slot] = t64;
+    return t32;
+}
+
+// FFT of the embedded symbol in double precision, natural order, scaled by 1/L.
+double *symbol_spectrum64(thx_plan *p, hipStream_t s)
+{
+    const int64_t L = p->L;
+    double *emb = dalloc<double>(2 * L);
+    double *out = dalloc<double>(2 * L);
+    launch_symbol_embed(p->tsym, p->nc, emb, L, s);
+    launch_check();
+    std::vector<void *> tmp;
+    if (L <= lds_max_len<double>()) {
+        double *tw = dalloc<double>(2 * L);
+        tmp.push_back(tw);
+        launch_twiddles(tw, nullptr, L, L, s);
+        if (!launch_fft_lds<double>(L, emb, out, tw, 1.0 / (double)L, s)) throw HipFail{hipErrorInvalidValue};
+        launch_check();
+    } else {
+        MultiPassGeom g = multipass_geom<double>(L);
+        double *twL1 = dalloc<double>(2 * g.L1), *twL2 = dalloc<double>(2 * g.L2),
+               *twA = dalloc<double>(2 * g.L1);
+        double *U = dalloc<double>(2 * L), *perm = dalloc<double>(2 * L);
+        tmp.insert(tmp.end(), {twL1, twL2, twA, U, perm});
+        launch_twiddles(twL1, nullptr, g.L1, g.L1, s);
+        launch_twiddles(twL2, nullptr, g.L2, g.L2, s);
+        launch_twiddles(twA, nullptr, L, g.L1, s);
+        if (!launch_mp_p1<double>(g, nullptr, 0, 0, nullptr, 0, 1, emb, U, 1, twL2, twA, s))
+            throw HipFail{hipErrorInvalidValue};
+        if (!launch_mp_p2<double>(g, U, 1, 1, nullptr, twL1, twA, twL2, false, perm, 1.0 / (double)L, s))
+            throw HipFail{hipErrorInvalidValue};
+        // perm[k2 L1 + k1] = spectrum[k2 + L2 k1]  ->  natural order
+        launch_reorder<double>(perm, out, L, g.L1, g.L2, 1, s);
+        launch_check();
+    }
+    hip_check(hipStreamSynchronize(s));
+    for (void *q : tmp) dfree(q);
+    dfree(emb);
+    return out;
+}
+
+void build_tables(thx_plan *p, hipStream_t s)
+{
+    const int64_t nt = p->nc, nh = 2 * p->nc + 2;
+    switch (p->kind) {
+    case THX_LEG2CHEB: {
+        // T_jk = Lambda((k-j)/2), H_jk = Lambda((j+k)/2): one table Lambda(m)
+        p->hk = dalloc<double>(nh);
+        launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(0.5, 1.0), 1.0, s);
+        p->tsym = p->hk;
+        p->tsym_alias = true;
+        break;
+    }
+    case THX_CHEB2LEG: {
+        // t_m = Gamma(m - 1/2)/Gamma(m + 1); h(s) = Gamma(s)/Gamma(s + 3/2), h(0) := 1
+        p->tsym = dalloc<double>(nt);
+        p->hk = dalloc<double>(nh);
+        launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(-0.5, 1.0), 1.0, s);
+        launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(0.0, 1.5), 1.0, s);
+        launch_set_value(p->hk, 1.0, s);
+        break;
+    }
+    case THX_ULTRA2ULTRA: {
+        const double l1 = p->params[0], l2 = p->params[1], dl = l1 - l2;
+        p->tsym = dalloc<double>(nt);
+        p->hk = dalloc<double>(nh);
+        // t_m = (dl)_m / m! = Gamma(m + dl) / (Gamma(dl) Gamma(m + 1)); dl = 0 is the identity
+        if (dl == 0.0) {
+            hip_check(hipMemsetAsync(p->tsym, 0, sizeof(double) * nt, s));
+            launch_set_value(p->tsym, 1.0, s);
+        } else {
+            launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
+        }
+        // h(s) = (l1)_s / (l2)_{s+1} = Gamma(s + l1) Gamma(l2) / (Gamma(l1) Gamma(s + l2 + 1))
+        launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(l1, l2 + 1.0),
+                           std::exp(std::lgamma(l2) - std::lgamma(l1)), s);
+        break;
+    }
+    case THX_LAG2LAG: {
+        const double dl = p->params[0] - p->params[1];
+        p->tsym = dalloc<double>(nt);
+        p->hk = dalloc<double>(nh);
+        launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
+        // Hankel part = all ones (Sec. 5.4): Gamma(s+1)/Gamma(s+1)
+        launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(1.0, 1.0), 1.0, s);
+        break;
+    }
+    default: throw HipFail{hipErrorInvalidValue};
+    }
+    launch_check();
+}
+
+void run_pchol(thx_plan *p, hipStream_t s)
+{
+    const int64_t maxn = std::max(p->npart[0] - p->a0[0], p->parts == 2 ? p->npart[1] - p->a0[1] : 0);
+    int kcap = (int)std::min<int64_t>(KMAX, std::max<int64_t>(maxn, 1));
+    p->slots_alloc = p->parts == 2 ? kcap : (kcap + 1) / 2;
+    p->ell64 = dalloc<double>(2 * (int64_t)p->slots_alloc * p->nc);
+    hip_check(hipMemsetAsync(p->ell64, 0, sizeof(double) * 2 * (size_t)p->slots_alloc * p->nc, s));
+    double *d = dalloc<double>((int64_t)p->parts * p->nc);
+    PcholState *st = dalloc<PcholState>(1);
+    hip_check(hipMemsetAsync(st, 0, sizeof(PcholState), s));
+    const int nblk = (int)((p->nc + 255) / 256);
+    double *pv = dalloc<double>((int64_t)p->parts * nblk);
+    int *pi = dalloc<int>((int64_t)p->parts * nblk);
+    PcholArgs a{};
+    a.hk = p->hk;
+    a.d = d;
+    a.ell = p->ell64;
+    a.nc = p->nc;
+    for (int q = 0; q < 2; ++q) {
+        a.n[q] = p->npart[q];
+        a.a0[q] = p->a0[q];
+    }
+    a.parts = p->parts;
+    a.tol = p->tol;
+    a.kcap = kcap;
+    a.st = st;
+    a.pv = pv;
+    a.pi = pi;
+    a.nblk = nblk;
+    launch_pchol_init(a, s);
+    launch_check();
+    PcholState hs;
+    for (int r = 0; r <= kcap; ++r) {
+        launch_pchol_step(a, r, s);
+        launch_check();
+        if (r % 8 == 7 || r == kcap) {
+            int done[2];
+            hip_check(hipMemcpyAsync(done, st->done, sizeof(done), hipMemcpyDeviceToHost, s));
+            hip_check(hipStreamSynchronize(s));
+            bool all = true;
+            for (int q = 0; q < p->parts; ++q) all = all && done[q];
+            if (all) break;
+        }
+    }
+    hip_check(hipMemcpyAsync(&hs, st, sizeof(PcholState), hipMemcpyDeviceToHost, s));
+    hip_check(hipStreamSynchronize(s));
+    for (int q = 0; q < p->parts; ++q) {
+        p->K[q] = hs.K[q];
+        p->dfinal[q] = hs.dfinal[q];
+        if (hs.K[q] >= kcap && hs.dfinal[q] > p->tol) p->tol_reached = false;
+        p->pivots[q] = new int32_t[std::max(1, hs.K[q])];
+        for (int r = 0; r < hs.K[q]; ++r) p->pivots[q][r] = hs.piv[q][r];
+    }
+    p->S = p->parts == 2 ? std::max(p->K[0], p->K[1]) : (p->K[0] + 1) / 2;
+    dfree(d);
+    dfree(st);
+    dfree(pv);
+    dfree(pi);
+}
+
+void build_fft(thx_plan *p, hipStream_t s)
+{
+    p->L = std::max<int64_t>(64, next_pow2(2 * p->nc - 2));
+    if (p->L > ((int64_t)1 << 22)) throw std::invalid_argument("L");
+    run_pchol(p, s);
+    const bool f64 = p->prec == THX_FP64;
+    if (!f64) {
+        p->ell32 = dalloc<float>(2 * (int64_t)std::max(p->S, 1) * p->nc);
+        launch_cast(p->ell64, p->ell32, 2 * (int64_t)p->S * p->nc, s);
+        launch_check();
+    }
+    double *spec = symbol_spectrum64(p, s); // natural order, scaled by 1/L
+    const int64_t L = p->L;
+    const int64_t lmax = f64 ? lds_max_len<double>() : lds_max_len<float>();
+    if (L <= lmax) {
+        p->path = 1;
+        p->twL = make_twiddles(p, L, L, s, 0);
+        if (f64) {
+            p->that = spec;
+            spec = nullptr;
+        } else {
+            p->that = dalloc<char>((int64_t)p->esize() * L);
+            launch_reorder<float>(spec, p->that, L, 0, 0, 0, s);
+            launch_check();
+        }
+    } else {
+        p->path = 2;
+        p->geom = f64 ? multipass_geom<double>(L) : multipass_geom<float>(L);
+        const MultiPassGeom &g = p->geom;
+        p->twL1 = make_twiddles(p, g.L1, g.L1, s, 0);
+        p->twL2 = make_twiddles(p, g.L2, g.L2, s, 1);
+        p->twA = make_twiddles(p, L, g.L1, s, 2);
+        // permuted symbol: perm[k2 L1 + k1] = spectrum[k2 + L2 k1]
+        p->that = dalloc<char>((int64_t)p->esize() * L);
+        if (f64) launch_reorder<double>(spec, p->that, L, g.L1, g.L2, 2, s);
+        else launch_reorder<float>(spec, p->that, L, g.L1, g.L2, 2, s);
+        launch_check();
+    }
+    dfree(spec);
+    hip_check(hipStreamSynchronize(s));
+}
+
+thx_status validate_kind(thx_kind kind, const double *params, int nparams, double *out)
+{
+    auto need = [&](int n) { return nparams >= n && params != nullptr; };
+    switch (kind) {
+    case THX_LEG2CHEB:
+    case THX_CHEB2LEG: return THX_OK;
+    case THX_ULTRA2ULTRA: {
+        if (!need(2)) return THX_INVALID_ARGUMENT;
+        const double l1 = params[0], l2 = params[1];
+        if (!(l1 > 0) || !(l2 > 0) || !std::isfinite(l1) || !std::isfinite(l2)) return THX_INVALID_ARGUMENT;
+        const double dl = l1 - l2;
+        // Hankel part PSD needs l1 - l2 <= 1 (Sec. 5.2, case 2); integer differences
+        // other than 0 and 1 are the banded case 1
+        if (dl > 1.0) return THX_UNSUPPORTED;
+        if (dl <= 0 && dl == std::floor(dl)) return dl == 0 ? THX_OK : THX_UNSUPPORTED;
+        out[0] = l1;
+        out[1] = l2;
+        return THX_OK;
+    }
+    case THX_LAG2LAG: {
+        if (!need(2)) return THX_INVALID_ARGUMENT;
+        const double a1 = params[0], a2 = params[1];
+        if (!(a1 > -1) || !(a2 > -1) || !std::isfinite(a1) || !std::isfinite(a2)) return THX_INVALID_ARGUMENT;
+        const double dl = a1 - a2;
+        if (dl <= 0 && dl == std::floor(dl)) return THX_UNSUPPORTED;
+        out[0] = a1;
+        out[1] = a2;
+        return THX_OK;
+    }
+    default: return THX_UNSUPPORTED;
+    }
+}
+
+thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
+                       double tol, thx_precision prec, uint32_t flags, hipStream_t s)
+{
+    if (!out) return THX_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (degree < 0 || !(tol > 0) || !(tol < 1) || (prec != THX_FP64 && prec != THX_FP32_BULK))
+        return THX_INVALID_ARGUMENT;
+    double pv[4] = {0, 0, 0, 0};
+    thx_status vs = validate_kind(kind, params, nparams, pv);
+    if (vs != THX_OK) return vs;
+    thx_plan *p = new (std::nothrow) thx_plan();
+    if (!p) return THX_OUT_OF_MEMORY;
+    p->kind = kind;
+    std::memcpy(p->params, pv, sizeof(pv));
+    p->N = degree;
+    p->tol = tol;
+    p->prec = prec;
+    p->flags = flags;
+    p->kd.kind = (int)kind;
+    p->kd.parity = (kind == THX_LEG2CHEB || kind == THX_CHEB2LEG || kind == THX_ULTRA2ULTRA) ? 1 : 0;
+    for (int i = 0; i < 4; ++i) p->kd.p[i] = pv[i];
+    if (p->kd.parity) {
+        p->parts = 2;
+        p->nc = degree / 2 + 1;
+        p->npart[0] = degree / 2 + 1;
+        p->npart[1] = (degree + 1) / 2;
+        p->a0[0] = (kind == THX_CHEB2LEG) ? 1 : 0;
+        p->a0[1] = 0;
+    } else {
+        p->parts = 1;
+        p->nc = degree + 1;
+        p->npart[0] = degree + 1;
+    }
+    try {
+        build_tables(p, s);
+        const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
+                            (!(flags & THX_FLAG_FORCE_FFT) && degree <= direct_crossover()) ||
+                            degree < 2 ||
+                            (kind == THX_ULTRA2ULTRA && p->params[0] == p->params[1]);
+        if (direct) {
+            p->path = 0;
+            hip_check(hipStreamSynchronize(s));
+        } else {
+            build_fft(p, s);
+        }
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        delete p;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return THX_OUT_OF_MEMORY;
+    } catch (const std::invalid_argument &) {
+        delete p;
+        return THX_UNSUPPORTED;
+    }
+    *out = p;
+    return p->tol_reached ? THX_OK : THX_TOL_NOT_REACHED;
+}
+
+void ensure_workspace(thx_plan *p, int64_t batch)
+{
+    if (batch <= p->ws_batch) return;
+    dfree(p->X);
+    dfree(p->Wp);
+    dfree(p->U);
+    dfree(p->row0);
+    p->X = p->Wp = p->U = nullptr;
+    p->row0 = nullptr;
+    p->ws_batch = 0;
+    const size_t es = p->esize();
+    p->X = dalloc<char>((int64_t)(es * (size_t)(batch * p->nc)));
+    p->Gmax = std::max(1, p->S);
+    p->Wp = dalloc<char>((int64_t)(es * (size_t)((int64_t)p->Gmax * batch * p->nc)));
+    p->row0 = dalloc<double>(batch);
+    if (p->path == 2) {
+        // slot chunk so that the FFT intermediates stay within ~2 GiB
+        const int64_t per = (int64_t)es * p->L * batch;
+        int64_t sc = std::max<int64_t>(1, ((int64_t)2 << 30) / per);
+        sc = std::min<int64_t>(sc, std::max(1, p->S));
+        p->U_slots = sc;
+        p->U = dalloc<char>(per * sc);
+    }
+    p->ws_batch = batch;
+}
+
+template <typename T>
+void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int64_t batch, int64_t ld,
+                 hipStream_t s)
+{
+    const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
+    const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
+    launch_pack<T>(p->kd, alpha, ld, N, batch, p->X, p->nc, s);
+    int G = 0;
+    if (p->S > 0) {
+        if (p->path == 1) {
+            int Gt = (int)std::min<int64_t>(p->S, std::max<int64_t>(1, (512 + batch - 1) / batch));
+            const int spg = (p->S + Gt - 1) / Gt;
+            G = (p->S + spg - 1) / spg;
+            if (!launch_toep_lds<T>(p->L, p->X, p->nc, n, ell, p->S, spg, G, p->that, p->twL, p->Wp, batch, s))
+                throw HipFail{hipErrorInvalidValue};
+        } else {
+            const MultiPassGeom &g = p->geom;
+            const int64_t tiles = g.L1 / g.TC;
+            for (int s0 = 0; s0 < p->S; s0 += (int)p->U_slots) {
+                const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
+                if (!launch_mp_p1<T>(g, p->X, p->nc, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
+                    throw HipFail{hipErrorInvalidValue};
+                if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
+                    throw HipFail{hipErrorInvalidValue};
+                int Gc = (int)std::min<int64_t>(ns, std::max<int64_t>(1, (1024 + tiles * batch - 1) / (tiles * batch)));
+                const int spg = (ns + Gc - 1) / Gc;
+                Gc = (ns + spg - 1) / spg;
+                if (!launch_mp_p3<T>(g, p->U, p->nc, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
+                    throw HipFail{hipErrorInvalidValue};
+                G += Gc;
+            }
+        }
+    } else {
+        hip_check(hipMemsetAsync(p->Wp, 0, p->esize() * (size_t)(batch * p->nc), s));
+        G = 1;
+    }
+    const double *row0 = nullptr;
+    if (p->kind == THX_CHEB2LEG) {
+        launch_row0_cheb2leg(p->kd, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
+        row0 = p->row0;
+    }
+    launch_unpack<T>(p->kd, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc, p->S,
+                     p->tsym, row0, s);
+    launch_check();
+}
+
+thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int64_t degree, int64_t batch,
+                      int64_t ld, hipStream_t s)
+{
+    thx_plan *p = const_cast<thx_plan *>(cp);
+    if (!p || degree < 0 || degree > p->N || batch < 0 || ld < degree + 1) return THX_INVALID_ARGUMENT;
+    if (batch == 0) return THX_OK;
+    if (!alpha || !beta) return THX_INVALID_ARGUMENT;
+    if (batch > 65535) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
+    try {
+        if (p->path == 0 || degree < 2) {
+            launch_direct(p->kd, alpha, ld, beta, degree, batch, p->tsym, p->hk, s);
+            launch_check();
+            return THX_OK;
+        }
+        ensure_workspace(p, batch);
+        if (p->prec == THX_FP64) execute_fft<double>(p, alpha, beta, degree, batch, ld, s);
+        else execute_fft<float>(p, alpha, beta, degree, batch, ld, s);
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        return THX_OUT_OF_MEMORY;
+    }
+    return THX_OK;
+}
+
+// ---- plan cache for the one-shot calls ----
+using Key = std::tuple<int, double, double, int64_t, double, int, int>;
+std::mutex g_cache_mu;
+std::map<Key, thx_plan *> g_cache;
+
+thx_status cached_convert(thx_kind kind, const double *params, int np, const double *alpha, double *beta,
+                          int64_t N, int64_t batch, double tol, thx_precision prec, hipStream_t s)
+{
+    if (N < 0) return THX_INVALID_ARGUMENT;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Key k{(int)kind, np > 0 ? params[0] : 0.0, np > 1 ? params[1] : 0.0, N, tol, (int)prec, dev};
+    thx_plan *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(k);
+        if (it != g_cache.end()) p = it->second;
+    }
+    if (!p) {
+        thx_status st = create_plan(&p, kind, params, np, N, tol, prec, 0, s);
+        if (st != THX_OK && st != THX_TOL_NOT_REACHED) return st;
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(k);
+        if (it != g_cache.end()) {
+            delete p;
+            p = it->second;
+        } else {
+            g_cache[k] = p;
+        }
+    }
+    return do_execute(p, alpha, beta, N, batch, N + 1, s);
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
+                           double tol, thx_precision prec, uint32_t flags, hipStream_t stream)
+{
+    return create_plan(out, kind, params, nparams, degree, tol, prec, flags, stream);
+}
+
+thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree, int64_t batch,
+                       int64_t ld, hipStream_t stream)
+{
+    return do_execute(plan, alpha, beta, degree, batch, ld, stream);
+}
+
+thx_status thx_plan_destroy(thx_plan *plan)
+{
+    delete plan;
+    return THX_OK;
+}
+
+int32_t thx_plan_rank(const thx_plan *p) { return p ? (p->path == 0 ? 0 : p->S) : -1; }
+int32_t thx_plan_rank_part(const thx_plan *p, int part)
+{
+    if (!p || part < 0 || part >= p->parts || p->path == 0) return -1;
+    return p->K[part];
+}
+int64_t thx_plan_fft_length(const thx_plan *p) { return p ? (p->path == 0 ? 0 : p->L) : -1; }
+int32_t thx_plan_path(const thx_plan *p) { return p ? p->path : -1; }
+double thx_plan_achieved_tol(const thx_plan *p, int part)
+{
+    if (!p || part < 0 || part >= p->parts || p->path == 0) return -1.0;
+    return p->dfinal[part];
+}
+
+thx_status thx_plan_factors(const thx_plan *p, int part, double *ell, int32_t *pivots, int64_t *n_out,
+                            hipStream_t stream)
+{
+    if (!p || part < 0 || part >= p->parts || p->path == 0) return THX_INVALID_ARGUMENT;
+    const int64_t n = p->npart[part];
+    if (n_out) *n_out = n;
+    if (pivots)
+        for (int r = 0; r < p->K[part]; ++r) pivots[r] = p->pivots[part][r];
+    if (!ell) return THX_OK;
+    try {
+        std::vector<double> h(2 * (size_t)p->slots_alloc * p->nc);
+        hip_check(hipMemcpyAsync(h.data(), p->ell64, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream));
+        hip_check(hipStreamSynchronize(stream));
+        for (int r = 0; r < p->K[part]; ++r)
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t idx = p->parts == 2 ? 2 * ((int64_t)r * p->nc + i) + part
+                                                  : 2 * ((int64_t)(r >> 1) * p->nc + i) + (r & 1);
+                ell[(int64_t)r * n + i] = h[idx];
+            }
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        return THX_HIP_ERROR;
+    }
+    return THX_OK;
+}
+
+thx_status thx_leg2cheb(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
+                        thx_precision prec, hipStream_t stream)
+{
+    return cached_convert(THX_LEG2CHEB, nullptr, 0, alpha, beta, N, batch, tol, prec, stream);
+}
+thx_status thx_cheb2leg(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
+                        thx_precision prec, hipStream_t stream)
+{
+    return cached_convert(THX_CHEB2LEG, nullptr, 0, alpha, beta, N, batch, tol, prec, stream);
+}
+thx_status thx_ultra2ultra(const double *alpha, double *beta, int64_t N, int64_t batch, double lambda1,
+                           double lambda2, double tol, thx_precision prec, hipStream_t stream)
+{
+    const double p[2] = {lambda1, lambda2};
+    return cached_convert(THX_ULTRA2ULTRA, p, 2, alpha, beta, N, batch, tol, prec, stream);
+}
+thx_status thx_lag2lag(const double *alpha, double *beta, int64_t N, int64_t batch, double alpha1,
+                       double alpha2, double tol, thx_precision prec, hipStream_t stream)
+{
+    const double p[2] = {alpha1, alpha2};
+    return cached_convert(THX_LAG2LAG, p, 2, alpha, beta, N, batch, tol, prec, stream);
+}
+
+thx_status thx_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!g_cache.empty()) (void)hipDeviceSynchronize();
+    for (auto &kv : g_cache) delete kv.second;
+    g_cache.clear();
+    return THX_OK;
+}
+
+thx_status thx_lambda_table(double *out, int64_t count, double z0, hipStream_t stream)
+{
+    if (count < 0 || (count > 0 && !out)) return THX_INVALID_ARGUMENT;
+    launch_gamma_ratio(out, count, z0, make_gamma_ratio(0.5, 1.0), 1.0, stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return THX_HIP_ERROR;
+    }
+    return THX_OK;
+}
+
+thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a, double b, hipStream_t stream)
+{
+    if (count < 0 || (count > 0 && !out) || !std::isfinite(a) || !std::isfinite(b)) return THX_INVALID_ARGUMENT;
+    launch_gamma_ratio(out, count, z0, make_gamma_ratio(a, b), 1.0, stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return THX_HIP_ERROR;
+    }
+    return THX_OK;
+}
+
+const char *thx_status_string(thx_status s)
+{
+    switch (s) {
+    case THX_OK: return "THX_OK";
+    case THX_INVALID_ARGUMENT: return "THX_INVALID_ARGUMENT";
+    case THX_UNSUPPORTED: return "THX_UNSUPPORTED";
+    case THX_TOL_NOT_REACHED: return "THX_TOL_NOT_REACHED";
+    case THX_OUT_OF_MEMORY: return "THX_OUT_OF_MEMORY";
+    case THX_HIP_ERROR: return "THX_HIP_ERROR";
+    }
+    return "THX_UNKNOWN";
+}
+
+int thx_last_hip_error(void) { return g_last_hip_error; }
+
+} // extern "C"

@@ -1,0 +1,113 @@
+"""C ABI checks that run without a GPU: exports and argument validation.
+
+Every function declared in include/thx.h must be exported by libthx.so, and
+the calls whose arguments are invalid must return THX_INVALID_ARGUMENT (or
+THX_UNSUPPORTED) before touching the device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "thx.h")
+LIB = os.path.join(ROOT, "paper_1604_07486_amd", "libthx.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(thx_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libthx.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ["thx_plan_create", "thx_execute", "thx_plan_destroy", "thx_leg2cheb", "thx_cheb2leg",
+                 "thx_ultra2ultra", "thx_lag2lag", "thx_lambda_table", "thx_status_string"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (thx_[a-z0-9_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        getattr(lib, n)  # resolvable through the dynamic loader
+
+
+def test_status_strings(lib):
+    lib.thx_status_string.restype = ctypes.c_char_p
+    for code, name in enumerate(["THX_OK", "THX_INVALID_ARGUMENT", "THX_UNSUPPORTED", "THX_TOL_NOT_REACHED",
+                                 "THX_OUT_OF_MEMORY", "THX_HIP_ERROR"]):
+        assert lib.thx_status_string(code).decode() == name
+
+
+def _create(lib, kind, params, degree, tol, prec=0, flags=0):
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_double * max(1, len(params)))(*params)
+    lib.thx_plan_create.restype = ctypes.c_int
+    lib.thx_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_uint32,
+                                    ctypes.c_void_p]
+    st = lib.thx_plan_create(ctypes.byref(h), kind, arr, len(params), degree, tol, prec, flags, None)
+    return st, h
+
+
+@pytest.mark.parametrize("kind,params,degree,tol,prec,expect", [
+    (0, (), -1, 1e-15, 0, 1),          # negative degree
+    (0, (), 10, 0.0, 0, 1),            # tol must be in (0, 1)
+    (0, (), 10, 1.5, 0, 1),
+    (0, (), 10, float("nan"), 0, 1),
+    (0, (), 10, 1e-15, 7, 1),          # unknown precision
+    (2, (), 10, 1e-15, 0, 1),          # ultra2ultra needs two parameters
+    (2, (-0.5, 0.5), 10, 1e-15, 0, 1), # lambda must be > 0
+    (2, (3.5, 0.5), 10, 1e-15, 0, 2),  # lambda1 - lambda2 > 1: Hankel part not PSD
+    (2, (0.5, 2.5), 10, 1e-15, 0, 2),  # negative integer difference: banded case
+    (4, (-1.5, 0.0), 10, 1e-15, 0, 1), # Laguerre parameter must be > -1
+    (9, (), 10, 1e-15, 0, 2),          # unknown kind
+])
+def test_plan_create_rejects(lib, kind, params, degree, tol, prec, expect):
+    st, h = _create(lib, kind, params, degree, tol, prec)
+    assert st == expect and not h.value
+
+
+def test_null_out_pointer(lib):
+    lib.thx_plan_create.restype = ctypes.c_int
+    assert lib.thx_plan_create(None, 0, None, 0, ctypes.c_int64(10), ctypes.c_double(1e-15), 0,
+                               ctypes.c_uint32(0), None) == 1
+
+
+def test_execute_rejects_null_plan(lib):
+    lib.thx_execute.restype = ctypes.c_int
+    lib.thx_execute.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64] * 3 + [ctypes.c_void_p]
+    assert lib.thx_execute(None, None, None, 10, 1, 11, None) == 1
+
+
+def test_introspection_null_plan(lib):
+    lib.thx_plan_rank.restype = ctypes.c_int32
+    lib.thx_plan_path.restype = ctypes.c_int32
+    lib.thx_plan_fft_length.restype = ctypes.c_int64
+    lib.thx_plan_destroy.restype = ctypes.c_int
+    assert lib.thx_plan_rank(None) == -1
+    assert lib.thx_plan_path(None) == -1
+    assert lib.thx_plan_fft_length(None) == -1
+    assert lib.thx_plan_destroy(None) == 0
+
+
+def test_table_rejects_negative_count(lib):
+    lib.thx_lambda_table.restype = ctypes.c_int
+    lib.thx_lambda_table.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p]
+    assert lib.thx_lambda_table(None, -1, 0.0, None) == 1
+    assert lib.thx_lambda_table(None, 5, 0.0, None) == 1

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error measure (Sec. 4 reports absolute max error; the targets are relative):
+    err = max_j |beta_gpu_j - beta_oracle_j| / ||alpha||_1
+Bars: 1e-13 for THX_FP64 and 5e-6 for THX_FP32_BULK.  Small and medium sizes
+compare every output; the full sizes compare seeded sampled rows the oracle
+evaluates one by one.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07486_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-13, 5e-6
+EPS64, EPS32 = 1e-15, 1e-7
+
+
+@pytest.fixture(scope="module")
+def thx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1604_07486_amd import binding
+    return binding
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _run(thx, kind, N, prec, params=(), flags=0, p=1.0, seed=0, batch=None, tol=None, rows=None):
+    print(f"[case] kind={kind} N={N} prec={prec} params={params} flags={flags} batch={batch} seed={seed}",
+          flush=True)
+    import torch
+    tol = tol if tol is not None else (EPS64 if prec == thx.FP64 else EPS32)
+    alpha = inputs.coeffs(N, p, seed=seed, batch=batch)
+    plan = thx.Plan(kind, N, tol, prec, params=params, flags=flags)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    return plan, alpha, b.cpu().numpy()
+
+
+ORACLE_KIND = {0: "leg2cheb", 1: "cheb2leg", 2: "ultra2ultra", 4: "lag2lag"}
+
+
+def _err(got, ref, alpha):
+    return float(np.max(np.abs(got - ref)) / np.sum(np.abs(alpha)))
+
+
+def _check_full(thx, kind, N, prec, params=(), flags=0, p=1.0, seed=0, bar=None, tol=None):
+    plan, alpha, got = _run(thx, kind, N, prec, params, flags, p, seed, tol=tol)
+    ref = oracle.matvec(ORACLE_KIND[kind], alpha, params)
+    err = _err(got, ref, alpha)
+    bar = bar if bar is not None else (TOL64 if prec == thx.FP64 else TOL32)
+    print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < bar, (kind, N, prec, err)
+    return plan, err
+
+
+# ---------------------------------------------------------------------------
+# a1: Lambda / Gamma-ratio tables
+# ---------------------------------------------------------------------------
+
+def test_lambda_table_vs_oracle(thx):
+    import torch
+    M = (1 << 22) + 5
+    out = torch.empty(M, dtype=torch.float64, device="cuda:0")
+    thx.thx_lambda_table(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.lambda_table(M - 1)
+    rel = np.abs(got / ref - 1)
+    print(f"  lambda max rel err {rel.max():.3e} at {int(rel.argmax())}", flush=True)
+    assert rel.max() < 8 * 2.0 ** -53
+
+
+@pytest.mark.parametrize("a,b", [(-0.5, 1.0), (0.0, 1.5), (1.0, 2.5), (0.75, 1.0), (1.5, 1.5), (0.25, 1.75)])
+def test_gamma_ratio_table_vs_mpmath(thx, a, b):
+    import mpmath
+    import torch
+    z = np.array([0, 1, 2, 3, 5, 9, 10.5, 11, 12, 13, 40, 1000, 123456, 2 ** 21], dtype=np.float64)
+    got = []
+    for z0 in z:
+        out = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        thx.thx_gamma_ratio_table(out, a, b, z0=float(z0))
+        got.append(out.item())
+    with mpmath.workdps(40):
+        for z0, g in zip(z, got):
+            ref = mpmath.gamma(z0 + a) / mpmath.gamma(z0 + b)
+            assert abs(g / float(ref) - 1) < 2e-14, (a, b, z0, g, ref)
+
+
+# ---------------------------------------------------------------------------
+# a2: pivoted Cholesky factors of the Hankel parts
+# ---------------------------------------------------------------------------
+
+def test_pchol_factors_reconstruct_hankel(thx):
+    N = 300
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64, flags=thx.FLAG_FORCE_FFT)
+    lam = oracle.lambda_table(N + 2)
+    for q in (0, 1):
+        ell, piv = plan.factors(q)
+        n = ell.shape[1]
+        i = np.arange(n)
+        H = lam[i[:, None] + i[None, :] + q]       # H_q(a, b) = Lambda(a + b + q)
+        E = H - ell.T @ ell
+        print(f"  part {q}: K={ell.shape[0]} max|H-LL^T|={np.abs(E).max():.3e}", flush=True)
+        assert np.abs(E).max() < 1e-14 * H.max()
+        assert piv[0] == int(np.argmax(np.diag(H)))
+        assert np.abs(E[piv, :]).max() < 1e-14
+        assert plan.achieved_tol(q) <= EPS64
+    # the paper reports 27 pivots for the full Hankel at N = 300 (Fig. 2); each
+    # parity half needs no more
+    assert plan.rank <= 27
+
+
+# ---------------------------------------------------------------------------
+# leg2cheb: every output at small and medium N
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 17, 64, 100, 255, 511, 512, 513, 1000, 2047, 2048, 2049, 4095, 4096,
+                               8189, 8190, 8191, 8192, 8193, 12345, 20000])
+def test_leg2cheb_fft_fp64(thx, N):
+    _check_full(thx, thx.LEG2CHEB, N, thx.FP64, flags=thx.FLAG_FORCE_FFT, seed=N)
+
+
+@pytest.mark.parametrize("N", [3, 100, 2048, 8192, 16384, 16385, 40000])
+def test_leg2cheb_fft_fp32(thx, N):
+    _check_full(thx, thx.LEG2CHEB, N, thx.FP32_BULK, flags=thx.FLAG_FORCE_FFT, seed=N)
+
+
+@pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 512])
+def test_leg2cheb_direct(thx, N):
+    _check_full(thx, thx.LEG2CHEB, N, thx.FP64, flags=thx.FLAG_FORCE_DIRECT, seed=N)
+
+
+@pytest.mark.parametrize("p", [0.0, 0.5, 2.0])
+def test_leg2cheb_decays(thx, p):
+    # Sec. 4 experiments: coefficient decay O(n^-p); undecayed vectors too
+    _check_full(thx, thx.LEG2CHEB, 30000, thx.FP64, flags=thx.FLAG_FORCE_FFT, p=p, seed=7)
+    _check_full(thx, thx.LEG2CHEB, 30000, thx.FP32_BULK, flags=thx.FLAG_FORCE_FFT, p=p, seed=7)
+
+
+def test_leg2cheb_batch_ld_and_subdegree(thx):
+    import torch
+    N, batch, ld = 5000, 5, 5013
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64, flags=thx.FLAG_FORCE_FFT)
+    alpha = inputs.coeffs(ld - 1, 1.0, seed=3, batch=batch)
+    a = _dev(alpha)
+    b = torch.full_like(a, 7.0)
+    for deg in (N, 3001, 2):
+        print(f"[case] batch={batch} ld={ld} degree={deg}", flush=True)
+        plan.execute(a, b, degree=deg)
+        torch.cuda.synchronize()
+        got = b.cpu().numpy()
+        for i in range(batch):
+            ref = oracle.matvec("leg2cheb", alpha[i, :deg + 1])
+            assert _err(got[i, :deg + 1], ref, alpha[i, :deg + 1]) < TOL64
+            assert np.all(got[i, N + 1:] == 7.0)   # entries beyond N untouched
+
+
+def test_leg2cheb_deterministic(thx):
+    import torch
+    N = 70000
+    alpha = inputs.coeffs(N, 1.0, seed=1)
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64)
+    a = _dev(alpha)
+    b1, b2 = torch.empty_like(a), torch.empty_like(a)
+    plan.execute(a, b1)
+    plan.execute(a, b2)
+    torch.cuda.synchronize()
+    assert torch.equal(b1, b2)
+
+
+def test_oneshot_leg2cheb_cache(thx):
+    import torch
+    N = 3000
+    alpha = inputs.coeffs(N, 1.0, seed=9)
+    a = _dev(alpha)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        thx.thx_leg2cheb(a, b, tol=EPS64)
+    torch.cuda.synchronize()
+    assert _err(b.cpu().numpy(), oracle.matvec("leg2cheb", alpha), alpha) < TOL64
+    thx.thx_cache_clear()
+
+
+def test_batch_zero_and_bad_args(thx):
+    import torch
+    plan = thx.Plan(thx.LEG2CHEB, 100, EPS64, thx.FP64)
+    a = torch.zeros(0, 101, dtype=torch.float64, device="cuda:0")
+    plan.execute(a, torch.zeros_like(a))
+    with pytest.raises(thx.ThxError):
+        x = torch.zeros(1, 101, dtype=torch.float64, device="cuda:0")
+        plan.execute(x, torch.zeros_like(x), degree=101)   # degree above the plan's
+
+
+# ---------------------------------------------------------------------------
+# leg2cheb at the full sizes: sampled rows
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,prec,p", [(1 << 20, 0, 1.5), (1 << 20, 1, 2.0), (1 << 20, 1, 0.0), (1 << 22, 0, 1.0),
+                                      (1 << 22, 1, 2.0)])
+def test_leg2cheb_full_size_sampled(thx, N, prec, p):
+    plan, alpha, got = _run(thx, thx.LEG2CHEB, N, prec, p=p, seed=N + prec)
+    rows = inputs.sample_rows(N, 256, seed=17)
+    ref = oracle.matvec("leg2cheb", alpha, rows=rows)
+    err = float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+    print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} sampled err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < (TOL64 if prec == 0 else TOL32)
+
+
+# ---------------------------------------------------------------------------
+# cheb2leg (Sec. 5.1), ultraspherical (Sec. 5.2), Laguerre (Sec. 5.4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [2, 3, 10, 600, 2048, 5001, 20000])
+def test_cheb2leg_fft_fp64(thx, N):
+    _check_full(thx, thx.CHEB2LEG, N, thx.FP64, flags=thx.FLAG_FORCE_FFT, p=1.5, seed=N, tol=1e-17)
+
+
+@pytest.mark.parametrize("N", [600, 9000])
+def test_cheb2leg_fft_fp32(thx, N):
+    _check_full(thx, thx.CHEB2LEG, N, thx.FP32_BULK, flags=thx.FLAG_FORCE_FFT, p=1.5, seed=N, tol=1e-9)
+
+
+@pytest.mark.parametrize("l1,l2,N", [(1.5, 0.5, 255), (1.5, 0.5, 3000), (0.75, 0.25, 1500), (1.0, 0.5, 9000),
+                                     (0.5, 1.25, 2000), (0.3, 0.3, 50)])
+def test_ultra2ultra(thx, l1, l2, N):
+    _check_full(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(l1, l2), flags=thx.FLAG_FORCE_FFT, seed=N)
+
+
+@pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000)])
+def test_lag2lag(thx, a1, a2, N):
+    _check_full(thx, thx.LAG2LAG, N, thx.FP64, params=(a1, a2), flags=thx.FLAG_FORCE_FFT, seed=N, p=1.0)
