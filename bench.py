@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the Toeplitz-dot-Hankel conversion on one MI355X.
+
+Headline workload: Legendre -> Chebyshev, one vector of degree N = 2^20,
+FP64 end to end, alpha_k = z_k (k+1)^-1.5 with z ~ N(0,1) (seeded), Hankel
+parts factorised to 1e-15.  A step is one execution of Fig. 1 steps 3-5
+(pack, K diagonally scaled Toeplitz products, D1) on a plan built once
+(steps 1-2 and the symbol FFT; the plan is reused as Sec. 2.1 suggests), with
+alpha already resident in HBM.  Plan construction is timed separately.
+
+Printed: one JSON line with the contract fields, the roofline of the dominant
+kernel (HIP-event timings of every launch in the timed region) and the CPU
+oracle timed on a bounded sample of output rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "leg2cheb coeffs/s at N=2^20 & batched; HBM GB/s; FP32 vs FP64 at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline timed loop (for profiler runs)")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the headline loop in --headline-only mode")
+    return ap.parse_args()
+
+
+def phase_bytes(phase, es, S, nc, L, G, batch=1):
+    """Algorithmic HBM bytes of one launch of `phase` (single rank chunk).
+
+    es: bytes per complex element; S: FFT slots in the launch; nc: complex lanes
+    of the input; L: FFT length; G: partial-sum groups.  Each term is data the
+    launch must read or write at least once: the normalised Cholesky columns
+    (S nc), the packed input (nc per vector), the FFT intermediates (S L per
+    vector, written by the forward column pass, read and written by the row
+    pass, read by the inverse column pass), the symbol spectrum (L) and the
+    partial sums (G nc per vector)."""
+    if phase == "col_fwd":
+        return es * (S * nc + batch * nc + S * batch * L)
+    if phase == "row":
+        return es * (2 * S * batch * L + L)
+    if phase == "col_inv":
+        return es * (S * batch * L + S * nc + G * batch * nc)
+    if phase == "toep_lds":
+        return es * (S * nc + batch * nc + L + G * batch * nc)
+    return None
+
+
+def time_plan(thx, torch, plan, a, b, steps, warmup):
+    for _ in range(warmup):
+        plan.execute(a, b)
+    torch.cuda.synchronize()
+    plan.timings(reset=True)
+    plan.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(a, b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.enable_timing(False)
+    return (t1 - t0) * 1e3 / steps, plan.timings(reset=True)
+
+
+def sampled_error(oracle, kind, alpha, got, rows):
+    ref = oracle.matvec(kind, alpha, rows=rows)
+    return float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this library runs on a single GPU; --gpus must be 1 "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1604_07486_amd import binding as thx
+    from paper_1604_07486_amd import inputs
+
+    dev = torch.device("cuda:0")
+    N = 1 << args.log2n
+    alpha = inputs.coeffs(N, 1.5, seed=20)
+    a = torch.from_numpy(alpha).to(dev)
+    b = torch.empty_like(a)
+
+    if args.headline_only:
+        prec = thx.FP64 if args.prec == "fp64" else thx.FP32_BULK
+        plan = thx.Plan(thx.LEG2CHEB, N, 1e-15 if prec == thx.FP64 else 1e-7, prec)
+        ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
+        print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms,
+                          "K": plan.rank, "L": plan.fft_length,
+                          "phases_ms_avg": {k: v[0] / v[1] for k, v in tim.items()}}), flush=True)
+        return
+
+    import oracle
+
+    # ---- plan (Fig. 1 steps 1-2 + symbol FFT), timed cold ----
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+
+    ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
+    value = (N + 1) / (ms * 1e-3)
+    rows = inputs.sample_rows(N, 256, seed=17)
+    err64 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
+
+    # ---- roofline of the dominant kernel (live HIP-event timings) ----
+    S, L = plan.rank, plan.fft_length
+    nc = N // 2 + 1
+    es = 16
+    dom = max(tim.items(), key=lambda kv: kv[1][0])
+    dname, (dtot, dcount) = dom
+    davg_ms = dtot / dcount
+    # partial-sum groups of the inverse column pass (as chosen by the library)
+    L1 = 4096
+    L2 = L // L1 if L > L1 else 1
+    TC = min(64, 4096 // max(L2, 1))
+    tiles = L1 // TC
+    Gc = min(S, max(1, -(-1024 // tiles)))
+    spg = -(-S // Gc)
+    Gc = -(-S // spg)
+    dbytes = phase_bytes(dname, es, S, nc, L, Gc)
+    roof = None
+    if dbytes is not None:
+        achieved = dbytes / (davg_ms * 1e-3) / 1e9
+        roof = {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": dbytes, "avg_launch_ms": round(davg_ms, 5), "launches": dcount}
+    # whole-step algorithmic bytes (all phases) over the step time
+    step_bytes = sum(phase_bytes(p, es, S, nc, L, Gc) or 0 for p in ("col_fwd", "row", "col_inv")) \
+        + 8 * 2 * (N + 1) + es * nc * (1 + Gc)
+
+    # ---- FP32-bulk at the same N (Lambda, Cholesky, D1/D2 in FP64) ----
+    plan32 = thx.Plan(thx.LEG2CHEB, N, 1e-7, thx.FP32_BULK)
+    ms32, tim32 = time_plan(thx, torch, plan32, a, b, args.steps, args.warmup)
+    err32 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
+    K32 = plan32.rank
+    del plan32
+
+    # ---- Chebyshev -> Legendre at the same N (Sec. 5.1) ----
+    planc = thx.Plan(thx.CHEB2LEG, N, 1e-17, thx.FP64)
+    msc, _ = time_plan(thx, torch, planc, a, b, max(5, args.steps // 2), 2)
+    errc = sampled_error(oracle, "cheb2leg", alpha, b.cpu().numpy(), rows)
+    Kc = planc.rank
+    del planc
+
+    # ---- CPU oracle on a bounded sample of output rows ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        g = inputs.rng(99)
+        done_rows, t_used = 0, 0.0
+        chunk = 64
+        while t_used < args.cpu_seconds:
+            r = g.integers(0, N + 1, size=chunk)
+            t0 = time.perf_counter()
+            oracle.matvec("leg2cheb", alpha, rows=r, nthreads=threads)
+            t_used += time.perf_counter() - t0
+            done_rows += chunk
+            chunk = min(chunk * 2, 4096)
+        rows_per_s = done_rows / t_used
+        cpu = {"value": round(rows_per_s, 2), "unit": "coeffs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{done_rows} uniformly random output rows of leg2cheb at N=2^20 "
+                         f"(O(N) each, extended precision) in {t_used:.1f} s; a full conversion "
+                         f"would take (N+1)/value = {(N + 1) / rows_per_s:.0f} s (extrapolated)"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "leg2cheb N=2^20 (1048577 coefficients), batch 1, FP64 end to end, "
+                               "alpha_k ~ N(0,1)(k+1)^-1.5 seed 20, Hankel tol 1e-15, plan reused",
+                   "N": N, "batch": 1, "K": S, "L": L, "path": plan.path},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": {"fp64_max_err_over_l1": err64, "fp64_bar": 1e-13,
+                     "rows_checked": int(len(rows))},
+        "plan_ms": round(plan_ms, 2),
+        "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+        "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim.items()},
+        "fp32_bulk": {"coeffs_per_s": round((N + 1) / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 5),
+                      "K": K32, "max_err_over_l1": err32, "bar": 5e-6, "hankel_tol": 1e-7,
+                      "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim32.items()}},
+        "cheb2leg_fp64": {"coeffs_per_s": round((N + 1) / (msc * 1e-3), 1), "ms_per_step": round(msc, 5),
+                          "K": Kc, "max_err_over_l1": errc, "hankel_tol": 1e-17},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

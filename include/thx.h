@@ -136,6 +136,27 @@ thx_status thx_lambda_table(double *out, int64_t count, double z0, hipStream_t s
 thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a, double b,
                                  hipStream_t stream);
 
+/* Per-phase GPU timing of thx_execute (tracing).  While enabled, each kernel
+ * launch of an execution is bracketed by hipEvents recorded on the execution's
+ * stream.  thx_plan_timings waits for the recorded events and writes, per
+ * phase, the summed milliseconds and the number of timed launches since the
+ * last reset (ms and launches: host arrays of THX_NPHASES entries, either may
+ * be NULL); reset != 0 clears the record.  At most 16384 launches are recorded
+ * between resets; later launches run untimed. */
+enum {
+    THX_PHASE_PACK = 0,     /* v = D2 alpha into complex lanes (Fig. 1 step 3)      */
+    THX_PHASE_TOEP_LDS = 1, /* single-workgroup Toeplitz products (step 4)          */
+    THX_PHASE_COL_FWD = 2,  /* three-pass FFT, forward column pass (step 4)         */
+    THX_PHASE_ROW = 3,      /* three-pass FFT, row pass with the symbol (step 4)    */
+    THX_PHASE_COL_INV = 4,  /* three-pass FFT, inverse column pass + rank sum       */
+    THX_PHASE_ROW0 = 5,     /* cheb2leg row 0 by a direct dot product               */
+    THX_PHASE_UNPACK = 6,   /* beta = D1 w (Fig. 1 step 5)                          */
+    THX_PHASE_DIRECT = 7,   /* O(N^2) direct evaluation                             */
+    THX_NPHASES = 8
+};
+thx_status thx_plan_enable_timing(thx_plan *plan, int enable);
+thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);
+
 const char *thx_status_string(thx_status s);
 int thx_last_hip_error(void);
 

@@ -62,6 +62,8 @@ def _load():
         lib.orc_matvec.restype = ctypes.c_int
         lib.orc_dense.argtypes = [ctypes.c_int, dp, i64, dp]
         lib.orc_dense.restype = ctypes.c_int
+        lib.orc_absmax.argtypes = [ctypes.c_int, dp, i64]
+        lib.orc_absmax.restype = ctypes.c_double
         lib.orc_lambda.argtypes = [i64, dp]
         lib.orc_lambda.restype = ctypes.c_int
         lib.orc_lambda_str.argtypes = [i64, ctypes.c_char_p, ctypes.c_int]
@@ -112,6 +114,14 @@ def dense(kind: str, N: int, params=()) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle dense failed (rc={rc})")
     return A
+
+
+def absmax(kind: str, N: int, params=()) -> float:
+    """max_{j,k} |A_jk| of the (N+1)x(N+1) conversion matrix (O(N^2))."""
+    v = _load().orc_absmax(KINDS[kind], _dptr(_params(kind, params)), N)
+    if v < 0:
+        raise ValueError("orc_absmax failed")
+    return float(v)
 
 
 def lambda_table(M: int) -> np.ndarray:

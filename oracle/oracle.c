@@ -374,6 +374,39 @@ int orc_dense(int kind, const double *params, int64_t N, double *A)
     return 0;
 }
 
+/* max_{j,k} |A_jk| over the (N+1)x(N+1) matrix (O(N^2); used to scale error bars
+ * for conversions whose entries grow with N). */
+double orc_absmax(int kind, const double *params, int64_t N)
+{
+    orc_ctx C;
+    if (N < 0 || ctx_init(&C, kind, params, N)) return -1.0;
+    double best = 0.0;
+    double *e = (kind == ORC_JAC2JAC) ? (double *)calloc((size_t)(N + 1), sizeof(double)) : NULL;
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : best)
+    for (int64_t j = 0; j <= N; ++j) {
+        for (int64_t k = j; k <= N; ++k) {
+            double v;
+            if (kind == ORC_JAC2JAC) continue;
+            v = fabs((double)entry(&C, j, k));
+            if (v > best) best = v;
+        }
+    }
+    if (kind == ORC_JAC2JAC) {
+        /* Jacobi entries come from row_jacobi with unit vectors (small N only) */
+        for (int64_t k = 0; k <= N; ++k) {
+            e[k] = 1.0;
+            for (int64_t j = 0; j <= k; ++j) {
+                double v = fabs(row_jacobi(&C, j, e));
+                if (v > best) best = v;
+            }
+            e[k] = 0.0;
+        }
+        free(e);
+    }
+    ctx_free(&C);
+    return best;
+}
+
 /* Lambda(n) = Gamma(n+1/2)/Gamma(n+1), n = 0..M, rounded to double. */
 int orc_lambda(int64_t M, double *out)
 {

@@ -8,12 +8,12 @@ library libthx.so (C ABI in include/thx.h); this package only marshals
 arguments (see ``paper_1604_07486_amd.binding``).  The binding is imported
 lazily so that ``paper_1604_07486_amd.inputs`` works without the library.
 """
+import importlib
 
 __all__ = ["binding", "inputs"]
 
 
 def __getattr__(name):
-    if name == "binding":
-        from . import binding
-        return binding
+    if name in ("binding", "inputs"):
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -21,6 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG = 0, 1, 2, 3, 4
 FP64, FP32_BULK = 0, 1
 FLAG_FORCE_DIRECT, FLAG_FORCE_FFT = 1, 2
+PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct"]
 STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_TOL_NOT_REACHED",
           4: "THX_OUT_OF_MEMORY", 5: "THX_HIP_ERROR"}
 
@@ -53,6 +54,8 @@ _sig("thx_lag2lag", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes
 _sig("thx_cache_clear", ctypes.c_int)
 _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
+_sig("thx_plan_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
+_sig("thx_plan_timings", ctypes.c_int, _vp, _dp, ctypes.POINTER(_i64), ctypes.c_int)
 _sig("thx_status_string", ctypes.c_char_p, ctypes.c_int)
 _sig("thx_last_hip_error", ctypes.c_int)
 
@@ -131,6 +134,17 @@ class Plan:
                                      piv.ctypes.data_as(ctypes.POINTER(_i32)), ctypes.byref(n),
                                      _stream(stream)), "thx_plan_factors")
         return ell, piv[:max(K, 0)]
+
+    def enable_timing(self, on: bool = True):
+        _check(_lib.thx_plan_enable_timing(self._h, 1 if on else 0), "thx_plan_enable_timing")
+
+    def timings(self, reset: bool = True):
+        """{phase: (total_ms, launches)} of the timed executions since the last reset."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (_i64 * n)()
+        _check(_lib.thx_plan_timings(self._h, ms, cnt, 1 if reset else 0), "thx_plan_timings")
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(n) if cnt[i]}
 
     def execute(self, alpha, beta, degree=None, stream=None):
         """thx_execute on [batch][ld] (or [N+1]) float64 device tensors."""

@@ -127,6 +127,14 @@ struct thx_plan {
     double *row0 = nullptr;
     int64_t U_slots = 0;
     int Gmax = 0;
+    // per-phase event timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Mark {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
 
     size_t esize() const { return prec == THX_FP64 ? 16 : 8; }
     ~thx_plan()
@@ -156,6 +164,7 @@ struct thx_plan {
         dfree(row0);
         delete[] pivots[0];
         delete[] pivots[1];
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
 };
 
@@ -388,12 +397,12 @@ thx_status validate_kind(thx_kind kind, const double *params, int nparams, doubl
         const double l1 = params[0], l2 = params[1];
         if (!(l1 > 0) || !(l2 > 0) || !std::isfinite(l1) || !std::isfinite(l2)) return THX_INVALID_ARGUMENT;
         const double dl = l1 - l2;
+        out[0] = l1;
+        out[1] = l2;
         // Hankel part PSD needs l1 - l2 <= 1 (Sec. 5.2, case 2); integer differences
         // other than 0 and 1 are the banded case 1
         if (dl > 1.0) return THX_UNSUPPORTED;
-        if (dl <= 0 && dl == std::floor(dl)) return dl == 0 ? THX_OK : THX_UNSUPPORTED;
-        out[0] = l1;
-        out[1] = l2;
+        if (dl < 0 && dl == std::floor(dl)) return THX_UNSUPPORTED;
         return THX_OK;
     }
     case THX_LAG2LAG: {
@@ -470,6 +479,35 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
     return p->tol_reached ? THX_OK : THX_TOL_NOT_REACHED;
 }
 
+constexpr size_t MAX_MARKS = 16384;
+
+// Brackets one kernel launch with events when the plan's timing is on.
+struct PhaseTimer {
+    thx_plan *p;
+    hipStream_t s;
+    int phase;
+    hipEvent_t a = nullptr, b = nullptr;
+    PhaseTimer(thx_plan *p_, int ph, hipStream_t s_) : p(p_), s(s_), phase(ph)
+    {
+        if (!p->timing || p->marks.size() >= MAX_MARKS) return;
+        const size_t need = 2 * (p->marks.size() + 1);
+        while (p->ev_pool.size() < need) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e));
+            p->ev_pool.push_back(e);
+        }
+        a = p->ev_pool[need - 2];
+        b = p->ev_pool[need - 1];
+        hip_check(hipEventRecord(a, s));
+    }
+    ~PhaseTimer() noexcept(false)
+    {
+        if (!a) return;
+        hip_check(hipEventRecord(b, s));
+        p->marks.push_back({phase, a, b});
+    }
+};
+
 void ensure_workspace(thx_plan *p, int64_t batch)
 {
     if (batch <= p->ws_batch) return;
@@ -502,13 +540,17 @@ void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int6
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
-    launch_pack<T>(p->kd, alpha, ld, N, batch, p->X, p->nc, s);
+    {
+        PhaseTimer t(p, THX_PHASE_PACK, s);
+        launch_pack<T>(p->kd, alpha, ld, N, batch, p->X, p->nc, s);
+    }
     int G = 0;
     if (p->S > 0) {
         if (p->path == 1) {
             int Gt = (int)std::min<int64_t>(p->S, std::max<int64_t>(1, (512 + batch - 1) / batch));
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
+            PhaseTimer t(p, THX_PHASE_TOEP_LDS, s);
             if (!launch_toep_lds<T>(p->L, p->X, p->nc, n, ell, p->S, spg, G, p->that, p->twL, p->Wp, batch, s))
                 throw HipFail{hipErrorInvalidValue};
         } else {
@@ -516,15 +558,24 @@ void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int6
             const int64_t tiles = g.L1 / g.TC;
             for (int s0 = 0; s0 < p->S; s0 += (int)p->U_slots) {
                 const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
-                if (!launch_mp_p1<T>(g, p->X, p->nc, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
-                    throw HipFail{hipErrorInvalidValue};
-                if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
-                    throw HipFail{hipErrorInvalidValue};
+                {
+                    PhaseTimer t(p, THX_PHASE_COL_FWD, s);
+                    if (!launch_mp_p1<T>(g, p->X, p->nc, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
+                        throw HipFail{hipErrorInvalidValue};
+                }
+                {
+                    PhaseTimer t(p, THX_PHASE_ROW, s);
+                    if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
+                        throw HipFail{hipErrorInvalidValue};
+                }
                 int Gc = (int)std::min<int64_t>(ns, std::max<int64_t>(1, (1024 + tiles * batch - 1) / (tiles * batch)));
                 const int spg = (ns + Gc - 1) / Gc;
                 Gc = (ns + spg - 1) / spg;
-                if (!launch_mp_p3<T>(g, p->U, p->nc, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
-                    throw HipFail{hipErrorInvalidValue};
+                {
+                    PhaseTimer t(p, THX_PHASE_COL_INV, s);
+                    if (!launch_mp_p3<T>(g, p->U, p->nc, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
+                        throw HipFail{hipErrorInvalidValue};
+                }
                 G += Gc;
             }
         }
@@ -534,11 +585,15 @@ void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int6
     }
     const double *row0 = nullptr;
     if (p->kind == THX_CHEB2LEG) {
+        PhaseTimer t(p, THX_PHASE_ROW0, s);
         launch_row0_cheb2leg(p->kd, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
         row0 = p->row0;
     }
-    launch_unpack<T>(p->kd, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc, p->S,
-                     p->tsym, row0, s);
+    {
+        PhaseTimer t(p, THX_PHASE_UNPACK, s);
+        launch_unpack<T>(p->kd, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc, p->S,
+                         p->tsym, row0, s);
+    }
     launch_check();
 }
 
@@ -552,6 +607,7 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     if (batch > 65535) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
     try {
         if (p->path == 0 || degree < 2) {
+            PhaseTimer t(p, THX_PHASE_DIRECT, s);
             launch_direct(p->kd, alpha, ld, beta, degree, batch, p->tsym, p->hk, s);
             launch_check();
             return THX_OK;
@@ -719,6 +775,37 @@ thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a
         g_last_hip_error = (int)e;
         return THX_HIP_ERROR;
     }
+    return THX_OK;
+}
+
+thx_status thx_plan_enable_timing(thx_plan *p, int enable)
+{
+    if (!p) return THX_INVALID_ARGUMENT;
+    p->timing = enable != 0;
+    return THX_OK;
+}
+
+thx_status thx_plan_timings(thx_plan *p, double *ms, int64_t *launches, int reset)
+{
+    if (!p) return THX_INVALID_ARGUMENT;
+    double acc[THX_NPHASES] = {0};
+    int64_t cnt[THX_NPHASES] = {0};
+    for (const auto &m : p->marks) {
+        hipError_t e = hipEventSynchronize(m.b);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, m.a, m.b);
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            return THX_HIP_ERROR;
+        }
+        acc[m.phase] += (double)t;
+        cnt[m.phase] += 1;
+    }
+    for (int i = 0; i < THX_NPHASES; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    if (reset) p->marks.clear();
     return THX_OK;
 }
 

@@ -56,11 +56,16 @@ def _err(got, ref, alpha):
     return float(np.max(np.abs(got - ref)) / np.sum(np.abs(alpha)))
 
 
-def _check_full(thx, kind, N, prec, params=(), flags=0, p=1.0, seed=0, bar=None, tol=None):
+def _check_full(thx, kind, N, prec, params=(), flags=0, p=1.0, seed=0, bar=None, tol=None, scale_bar=False):
     plan, alpha, got = _run(thx, kind, N, prec, params, flags, p, seed, tol=tol)
     ref = oracle.matvec(ORACLE_KIND[kind], alpha, params)
     err = _err(got, ref, alpha)
-    bar = bar if bar is not None else (TOL64 if prec == thx.FP64 else TOL32)
+    # the bars are relative to ||alpha||_1 for matrices with entries of size
+    # O(1) (leg2cheb: max |M_jk| = 1); when the entries grow with N (e.g. the
+    # ultraspherical 3/2 -> 1/2 matrix has A_jk = 2j + 1) a rounding error of
+    # one unit is amplified by max |A_jk|, so the bar scales with it
+    scale = max(1.0, oracle.absmax(ORACLE_KIND[kind], N, params)) if scale_bar else 1.0
+    bar = (bar if bar is not None else (TOL64 if prec == thx.FP64 else TOL32)) * scale
     print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} err={err:.3e}", flush=True)
     assert np.all(np.isfinite(got))
     assert err < bar, (kind, N, prec, err)
@@ -96,6 +101,9 @@ def test_gamma_ratio_table_vs_mpmath(thx, a, b):
         got.append(out.item())
     with mpmath.workdps(40):
         for z0, g in zip(z, got):
+            if z0 + a == 0:   # pole of the numerator: the generator returns +inf
+                assert g == float("inf")
+                continue
             ref = mpmath.gamma(z0 + a) / mpmath.gamma(z0 + b)
             assert abs(g / float(ref) - 1) < 2e-14, (a, b, z0, g, ref)
 
@@ -238,7 +246,8 @@ def test_cheb2leg_fft_fp32(thx, N):
 @pytest.mark.parametrize("l1,l2,N", [(1.5, 0.5, 255), (1.5, 0.5, 3000), (0.75, 0.25, 1500), (1.0, 0.5, 9000),
                                      (0.5, 1.25, 2000), (0.3, 0.3, 50)])
 def test_ultra2ultra(thx, l1, l2, N):
-    _check_full(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(l1, l2), flags=thx.FLAG_FORCE_FFT, seed=N)
+    _check_full(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(l1, l2), flags=thx.FLAG_FORCE_FFT, seed=N,
+                scale_bar=True)
 
 
 @pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000)])

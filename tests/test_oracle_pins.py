@@ -174,6 +174,13 @@ def test_polynomial_identity(kind, src, dst, params, N):
         assert abs(float(lhs - rhs)) < 1e-14 * l1, (kind, x)
 
 
+@pytest.mark.parametrize("kind,params", [("leg2cheb", ()), ("cheb2leg", ()), ("ultra2ultra", (1.5, 0.5)),
+                                         ("jac2jac_b", (0.5, -0.25, -0.5)), ("lag2lag", (0.5, -0.25))])
+def test_absmax_matches_dense(kind, params):
+    N = 37
+    assert oracle.absmax(kind, N, params) == np.max(np.abs(oracle.dense(kind, N, params)))
+
+
 def test_rows_subset_matches_full():
     N = 3001
     alpha = inputs.coeffs(N, 1.0, seed=3)
