@@ -41,7 +41,29 @@ def parse():
                     help="run only the headline timed loop (for profiler runs)")
     ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a plain device copy of 512 MiB (bandwidth ceiling and the "
+                         "reference for HBM byte counters)")
     return ap.parse_args()
+
+
+COPY_BYTES = 512 << 20
+
+
+def copy_bandwidth(torch, reps=20):
+    """GB/s of a plain device-to-device copy of COPY_BYTES (read + write counted)."""
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del src, dst
+    return 2 * COPY_BYTES / dt / 1e9
 
 
 def phase_bytes(phase, es, S, nc, L, G, batch=1):
@@ -108,7 +130,8 @@ def main():
         prec = thx.FP64 if args.prec == "fp64" else thx.FP32_BULK
         plan = thx.Plan(thx.LEG2CHEB, N, 1e-15 if prec == thx.FP64 else 1e-7, prec)
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
-        print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms,
+        copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
+        print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
                           "K": plan.rank, "L": plan.fft_length,
                           "phases_ms_avg": {k: v[0] / v[1] for k, v in tim.items()}}), flush=True)
         return
@@ -167,6 +190,8 @@ def main():
     Kc = planc.rank
     del planc
 
+    copy_gbs = copy_bandwidth(torch)
+
     # ---- CPU oracle on a bounded sample of output rows ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,6 +233,7 @@ def main():
         "accuracy": {"fp64_max_err_over_l1": err64, "fp64_bar": 1e-13,
                      "rows_checked": int(len(rows))},
         "plan_ms": round(plan_ms, 2),
+        "copy_gbs_measured": round(copy_gbs, 1),
         "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
         "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim.items()},
         "fp32_bulk": {"coeffs_per_s": round((N + 1) / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 5),

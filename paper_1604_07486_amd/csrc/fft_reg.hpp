@@ -1,0 +1,289 @@
+// fft_reg.hpp -- register-resident Stockham FFT for one workgroup (gfx950).
+//
+// A workgroup of NT threads transforms NB interleaved sequences of length M
+// (sequence c, element i at logical position i*NB + c).  Each thread keeps
+// E = M*NB/NT complex values in registers.  The transform is a sequence of
+// radix-R stages (R = 16 while possible, then one stage of 2, 4 or 8); the
+// inverse runs the radices in reverse order.  Between stages the values are
+// exchanged through LDS (padded one slot per 16 to spread the banks); the
+// first stage reads its inputs from registers and the last stage leaves its
+// outputs in registers, so callers load and store global memory directly in
+// the stage layouts, which are coalesced:
+//
+//   input layout of a forward transform (= output layout of an inverse):
+//       v[p*R1 + r] holds position j + r*(M/R1) of sequence c
+//   output layout of a forward transform (= input layout of an inverse):
+//       v[p*RS + q] holds position j + q*(M/RS) of sequence c
+//   where w = threadIdx.x + NT*p, c = w % NB, j = w / NB, R1 / RS are the
+//   first / last forward radices.
+//
+// Stage with radix R after sub-transforms of size Ns: butterfly j reads
+// x[j + r M/R], multiplies by w_{Ns R}^{(j mod Ns) r}, applies the radix-R DFT
+// and writes y[(j/Ns) Ns R + (j mod Ns) + q Ns]  (Stockham autosort).
+#pragma once
+#include "thx_device.hpp"
+
+namespace thx {
+
+// forward radix of stage s for length M and largest radix RMAX (16, 8 or 4):
+// RMAX, RMAX, ..., then the remainder
+constexpr int nstages(int M, int RMAX)
+{
+    return ilog2(M) / ilog2(RMAX) + (ilog2(M) % ilog2(RMAX) ? 1 : 0);
+}
+constexpr int fwd_radix(int M, int s, int RMAX)
+{
+    return (s < ilog2(M) / ilog2(RMAX)) ? RMAX : (1 << (ilog2(M) % ilog2(RMAX)));
+}
+template <bool INV>
+constexpr int stage_radix(int M, int s, int RMAX)
+{
+    return INV ? fwd_radix(M, nstages(M, RMAX) - 1 - s, RMAX) : fwd_radix(M, s, RMAX);
+}
+// product of the radices before stage s
+template <bool INV>
+constexpr int stage_ns(int M, int s, int RMAX)
+{
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= stage_radix<INV>(M, i, RMAX);
+    return ns;
+}
+// threads for M*NB points with at least min(M, RMAX) values per thread
+constexpr int fft_threads(int M, int NB, int RMAX, int maxnt = 1024)
+{
+    return (M * NB / (M < RMAX ? M : RMAX)) > maxnt ? maxnt : (M * NB / (M < RMAX ? M : RMAX));
+}
+
+#ifndef THX_LDS_PAD
+#define THX_LDS_PAD 1
+#endif
+__device__ __forceinline__ int lds_pad(int i) { return THX_LDS_PAD ? i + (i >> 4) : i; }
+constexpr int lds_padded(int n) { return THX_LDS_PAD ? n + (n >> 4) : n; }
+
+// w_R^m = exp(-+ 2 pi i m / R) for the constant twiddles inside a radix-R DFT
+template <typename T, int R, int m, bool INV>
+__device__ __forceinline__ cpx<T> wconst()
+{
+    constexpr int mm = ((m % R) + R) % R;
+    // cos / sin of 2 pi mm / R for R | 16
+    constexpr int e = mm * (16 / R); // in units of 2 pi / 16
+    constexpr double C[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                              0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+    constexpr double S[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                              1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                              0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                              -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+    return cpx<T>{(T)C[e], (T)(INV ? S[e] : -S[e])};
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cpx<T> &a, cpx<T> &b)
+{
+    const cpx<T> t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+// in-place radix-4 DFT of (a, b, c, d) = x[0..3]
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> &x3)
+{
+    const cpx<T> a0 = cadd(x0, x2), a1 = csub(x0, x2);
+    const cpx<T> a2 = cadd(x1, x3), a3 = csub(x1, x3);
+    const cpx<T> mi = {a3.y, -a3.x}; // -i a3
+    x0 = cadd(a0, a2);
+    x2 = csub(a0, a2);
+    if constexpr (!INV) {
+        x1 = cadd(a1, mi);
+        x3 = csub(a1, mi);
+    } else {
+        x1 = csub(a1, mi);
+        x3 = cadd(a1, mi);
+    }
+}
+
+// Radix-R DFT in registers, R = R1 * R2 with input n = R2 n1 + n2 and output
+// k = k1 + R1 k2: DFT_R1 over n1, twiddle w_R^{n2 k1}, DFT_R2 over n2.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T> *v)
+{
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
+        dft2<T, INV>(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    } else {
+        constexpr int R1 = 4, R2 = R / 4; // R = 8: (4, 2); R = 16: (4, 4)
+        cpx<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            cpx<T> a = v[n2], b = v[R2 + n2], c = v[2 * R2 + n2], d = v[3 * R2 + n2];
+            dft4<T, INV>(a, b, c, d);
+            y[0 * R2 + n2] = a;
+            y[1 * R2 + n2] = b;
+            y[2 * R2 + n2] = c;
+            y[3 * R2 + n2] = d;
+        }
+        // twiddle y[k1][n2] *= w_R^{n2 k1}
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) {
+#pragma unroll
+            for (int n2 = 1; n2 < R2; ++n2) {
+                cpx<T> w;
+                // compile-time constant selection
+                switch (n2 * k1) {
+                case 1: w = wconst<T, R, 1, INV>(); break;
+                case 2: w = wconst<T, R, 2, INV>(); break;
+                case 3: w = wconst<T, R, 3, INV>(); break;
+                case 4: w = wconst<T, R, 4, INV>(); break;
+                case 6: w = wconst<T, R, 6, INV>(); break;
+                case 9: w = wconst<T, R, 9, INV>(); break;
+                default: w = cpx<T>{1, 0}; break;
+                }
+                y[k1 * R2 + n2] = cmul(y[k1 * R2 + n2], w);
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            if constexpr (R2 == 2) {
+                dft2<T, INV>(y[k1 * R2], y[k1 * R2 + 1]);
+                v[k1] = y[k1 * R2];
+                v[k1 + R1] = y[k1 * R2 + 1];
+            } else {
+                dft4<T, INV>(y[k1 * R2], y[k1 * R2 + 1], y[k1 * R2 + 2], y[k1 * R2 + 3]);
+                v[k1] = y[k1 * R2];
+                v[k1 + R1] = y[k1 * R2 + 1];
+                v[k1 + 2 * R1] = y[k1 * R2 + 2];
+                v[k1 + 3 * R1] = y[k1 * R2 + 3];
+            }
+        }
+    }
+}
+
+// twiddle factors w^{e1 r}, r = 1..R-1, from the table tw[e] = w_M^e (e < M):
+// w^1, w^2, w^4, w^8 are read and every other power is a product of at most
+// four of them; the factors are formed just before use to keep few registers
+// live.
+template <typename T, bool INV>
+__device__ __forceinline__ void twmul(cpx<T> &x, cpx<T> w)
+{
+    x = INV ? cmulc(x, w) : cmul(x, w);
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restrict__ tw, int e1)
+{
+    // The exponent is made opaque so that the table reads stay here: hoisted out
+    // of a caller's loop over ranks they would pin every stage's twiddles in
+    // registers and force spills.
+    asm volatile("" : "+v"(e1));
+    const cpx<T> w1 = tw[e1];
+    twmul<T, INV>(v[1], w1);
+    if constexpr (R == 2) return;
+    const cpx<T> w2 = tw[2 * e1];
+    twmul<T, INV>(v[2], w2);
+    const cpx<T> w3 = cmul(w1, w2);
+    twmul<T, INV>(v[3], w3);
+    if constexpr (R == 4) return;
+    const cpx<T> w4 = tw[4 * e1];
+    twmul<T, INV>(v[4], w4);
+    twmul<T, INV>(v[5], cmul(w1, w4));
+    twmul<T, INV>(v[6], cmul(w2, w4));
+    const cpx<T> w7 = cmul(w3, w4);
+    twmul<T, INV>(v[7], w7);
+    if constexpr (R == 8) return;
+    const cpx<T> w8 = tw[8 * e1];
+    twmul<T, INV>(v[8], w8);
+    twmul<T, INV>(v[9], cmul(w1, w8));
+    twmul<T, INV>(v[10], cmul(w2, w8));
+    twmul<T, INV>(v[11], cmul(w3, w8));
+    twmul<T, INV>(v[12], cmul(w4, w8));
+    twmul<T, INV>(v[13], cmul(cmul(w1, w4), w8));
+    twmul<T, INV>(v[14], cmul(cmul(w2, w4), w8));
+    twmul<T, INV>(v[15], cmul(w7, w8));
+}
+
+template <typename T, int M, int NB, int NT, int RMAX = 16>
+struct RegFFT {
+    static constexpr int E = M * NB / NT;
+    static constexpr int NS = nstages(M, RMAX);
+    static constexpr int R_FIRST = fwd_radix(M, 0, RMAX);
+    static constexpr int R_LAST = fwd_radix(M, NS - 1, RMAX);
+    static constexpr int LDS = lds_padded(M * NB);
+    static_assert(E * NT == M * NB && E % R_FIRST == 0 && E % R_LAST == 0, "elements per thread");
+
+    // logical position (i*NB + c) of register slot `slot` in the forward input layout
+    __device__ static __forceinline__ void in_pos(int slot, int &pos, int &c)
+    {
+        const int p = slot / R_FIRST, r = slot % R_FIRST;
+        const int w = (int)threadIdx.x + NT * p;
+        c = w % NB;
+        pos = w / NB + r * (M / R_FIRST);
+    }
+    // logical position in the forward output layout
+    __device__ static __forceinline__ void out_pos(int slot, int &pos, int &c)
+    {
+        const int p = slot / R_LAST, q = slot % R_LAST;
+        const int w = (int)threadIdx.x + NT * p;
+        c = w % NB;
+        pos = w / NB + q * (M / R_LAST);
+    }
+
+    template <bool INV, int s>
+    __device__ static __forceinline__ void stages(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
+    {
+        if constexpr (s < NS) {
+            constexpr int R = stage_radix<INV>(M, s, RMAX);
+            constexpr int Ns = stage_ns<INV>(M, s, RMAX);
+            constexpr int PB = E / R; // butterflies per thread
+            static_assert(PB * R == E, "radix divides the per-thread count");
+            if constexpr (s > 0) {
+                // values are in LDS at the positions written by the previous stage
+#pragma unroll
+                for (int p = 0; p < PB; ++p) {
+                    const int w = (int)threadIdx.x + NT * p;
+                    const int c = w % NB, j = w / NB;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[p * R + r] = lds[lds_pad((j + r * (M / R)) * NB + c)];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const int w = (int)threadIdx.x + NT * p;
+                const int j = w / NB;
+                if constexpr (Ns > 1) apply_twiddles<T, R, INV>(v + p * R, tw, (j % Ns) * (M / (Ns * R)));
+                dft<T, R, INV>(v + p * R);
+            }
+            if constexpr (s + 1 < NS) {
+#pragma unroll
+                for (int p = 0; p < PB; ++p) {
+                    const int w = (int)threadIdx.x + NT * p;
+                    const int c = w % NB, j = w / NB;
+                    const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) lds[lds_pad((base + q * Ns) * NB + c)] = v[p * R + q];
+                }
+                __syncthreads();
+            }
+            stages<INV, s + 1>(v, lds, tw);
+        }
+    }
+
+    // forward: input layout -> output layout.  `lds` must hold LDS elements;
+    // the caller needs no barrier before the call, and one before the next
+    // use of `lds` only if it writes it itself.
+    __device__ static __forceinline__ void forward(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
+    {
+        stages<false, 0>(v, lds, tw);
+    }
+    // inverse (unnormalised): output layout -> input layout
+    __device__ static __forceinline__ void inverse(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
+    {
+        stages<true, 0>(v, lds, tw);
+    }
+};
+
+} // namespace thx

@@ -9,6 +9,7 @@
 //   a6  beta = D1 w (+ circulant alias term, special row) ...... k_unpack, k_row0
 // plus the O(N^2) direct evaluation used below the FFT crossover (Sec. 4).
 #include "launch.hpp"
+#include "fft_reg.hpp"
 #include "thx_device.hpp"
 #include <math.h>
 
@@ -491,27 +492,31 @@ void launch_direct(const KindDesc &k, const double *alpha, int64_t ld, double *b
 // a5: sums of diagonally scaled Toeplitz products, eq. (Cdecomposition)
 // ============================================================================
 
-template <int L>
-constexpr int lds_threads() { return L / 4 < 64 ? 64 : (L / 4 > 256 ? 256 : L / 4); }
+// Largest radix of the register FFTs.  Radix 8 keeps 8 values per thread, so a
+// workgroup of M*NB/8 threads holds the transform: twice the waves of radix 16
+// at the same LDS footprint, which is what hides HBM latency in these passes.
+constexpr int RMAX = 8;
+template <int M, int NB>
+constexpr int nthreads() { return fft_threads(M, NB, RMAX); }
 
 // One workgroup per (slot group, vector): for each slot s of the group
 //   z = l~_s o X (zero-padded to L) -> FFT -> . that -> IFFT -> acc += l~_s o y
-// with `that` = FFT(symbol)/L.  The accumulator stays in registers.
+// with `that` = FFT(symbol)/L.  The accumulator stays in registers, in the
+// forward-input layout that the inverse transform returns to.
 template <typename T, int L>
-__global__ __launch_bounds__(lds_threads<L>()) void k_toep_lds(
+__global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int S,
     int spg, const cpx<T> *__restrict__ that, const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ W,
     int64_t batch)
 {
-    constexpr int NT = lds_threads<L>();
-    constexpr int E = L / NT;
-    __shared__ cpx<T> buf[L];
+    using F = RegFFT<T, L, 1, nthreads<L, 1>(), RMAX>;
+    constexpr int E = F::E;
+    __shared__ cpx<T> lds[F::LDS];
     const int g = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int s0 = g * spg;
     const int s1 = min(S, s0 + spg);
-    const int tid = threadIdx.x;
-    cpx<T> acc[E];
+    cpx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
     const cpx<T> *Xb = X + b * nc;
@@ -519,45 +524,54 @@ __global__ __launch_bounds__(lds_threads<L>()) void k_toep_lds(
         const cpx<T> *es = ell + (int64_t)s * nc;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = tid + e * NT;
-            cpx<T> z = {0, 0};
-            if (i < n) z = cdiag(es[i], Xb[i]);
-            buf[i] = z;
+            int pos, c;
+            F::in_pos(e, pos, c);
+            v[e] = pos < n ? cdiag(es[pos], Xb[pos]) : cpx<T>{0, 0};
         }
-        __syncthreads();
-        lds_fft<T, L, 1, NT, false>(buf, tw);
+        F::forward(v, lds, tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = tid + e * NT;
-            buf[i] = cmul(buf[i], that[i]);
+            int pos, c;
+            F::out_pos(e, pos, c);
+            v[e] = cmul(v[e], that[pos]);
         }
-        __syncthreads();
-        lds_fft<T, L, 1, NT, true>(buf, tw);
+        F::inverse(v, lds, tw);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int i = tid + e * NT;
-            if (i < n) acc[e] = cadd(acc[e], cdiag(es[i], buf[i]));
+            int pos, c;
+            F::in_pos(e, pos, c);
+            if (pos < n) acc[e] = cadd(acc[e], cdiag(es[pos], v[e]));
         }
-        __syncthreads();
     }
     cpx<T> *Wg = W + ((int64_t)g * batch + b) * nc;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int i = tid + e * NT;
-        if (i < n) Wg[i] = acc[e];
+        int pos, c;
+        F::in_pos(e, pos, c);
+        if (pos < n) Wg[pos] = acc[e];
     }
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(lds_threads<L>()) void k_fft_lds(const cpx<T> *in, cpx<T> *out,
-                                                             const cpx<T> *tw, T scale)
+__global__ __launch_bounds__((nthreads<L, 1>())) void k_fft_lds(const cpx<T> *in, cpx<T> *out,
+                                                                  const cpx<T> *tw, T scale)
 {
-    constexpr int NT = lds_threads<L>();
-    __shared__ cpx<T> buf[L];
-    for (int i = threadIdx.x; i < L; i += NT) buf[i] = in[i];
-    __syncthreads();
-    lds_fft<T, L, 1, NT, false>(buf, tw);
-    for (int i = threadIdx.x; i < L; i += NT) out[i] = cpx<T>{buf[i].x * scale, buf[i].y * scale};
+    using F = RegFFT<T, L, 1, nthreads<L, 1>(), RMAX>;
+    __shared__ cpx<T> lds[F::LDS];
+    cpx<T> v[F::E];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+        int pos, c;
+        F::in_pos(e, pos, c);
+        v[e] = in[pos];
+    }
+    F::forward(v, lds, tw);
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+        int pos, c;
+        F::out_pos(e, pos, c);
+        out[pos] = cpx<T>{v[e].x * scale, v[e].y * scale};
+    }
 }
 
 template <typename T, int L>
@@ -565,9 +579,9 @@ static void run_toep_lds(const void *X, int64_t nc, int64_t n, const void *ell, 
                          const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
 {
     dim3 grid((unsigned)G, (unsigned)batch);
-    k_toep_lds<T, L><<<grid, lds_threads<L>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
-                                                      S, spg, (const cpx<T> *)that,
-                                                      (const cpx<T> *)tw, (cpx<T> *)W, batch);
+    k_toep_lds<T, L><<<grid, nthreads<L, 1>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
+                                                         S, spg, (const cpx<T> *)that,
+                                                         (const cpx<T> *)tw, (cpx<T> *)W, batch);
 }
 
 template <typename T>
@@ -596,14 +610,14 @@ template <typename T>
 bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale, hipStream_t s)
 {
     switch (L) {
-#define THX_CASE(LL) case LL: k_fft_lds<T, LL><<<1, lds_threads<LL>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out, (const cpx<T> *)tw, (T)scale); return true;
+#define THX_CASE(LL) case LL: k_fft_lds<T, LL><<<1, nthreads<LL, 1>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out, (const cpx<T> *)tw, (T)scale); return true;
         THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
         THX_CASE(4096)
 #undef THX_CASE
     case 8192:
         if constexpr (sizeof(T) == 4) {
-            k_fft_lds<T, 8192><<<1, lds_threads<8192>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out,
-                                                                (const cpx<T> *)tw, (T)scale);
+            k_fft_lds<T, 8192><<<1, nthreads<8192, 1>(), 0, s>>>((const cpx<T> *)in, (cpx<T> *)out,
+                                                                  (const cpx<T> *)tw, (T)scale);
             return true;
         }
         return false;
@@ -624,12 +638,25 @@ template bool launch_fft_lds<float>(int64_t, const void *, void *, const void *,
 //   P3: inverse column DFTs over k2 give y[a1 + L1 a2] in natural order, which
 //       is scaled by l~_s and summed over the slots of the group.
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Map the 1-D block index b to (item, rep) so that the `reps` blocks that share
+// `item`'s data (a symbol row, an input tile) run back to back on one XCD.
+// Requires items % 8 == 0; otherwise reps of an item are simply consecutive.
+__device__ __forceinline__ void xcd_map(int b, int items, int reps, int &item, int &rep)
+{
+    if (items & 7) {
+        item = b / reps;
+        rep = b % reps;
+        return;
+    }
+    const int x = b & 7, m = b >> 3;
+    item = x + 8 * (m / reps);
+    rep = m % reps;
+}
+
 template <typename T> constexpr int mp_tile() { return sizeof(T) == 8 ? 4096 : 8192; }
 template <typename T, int L2> constexpr int mp_tc() { return mp_tile<T>() / L2 > 64 ? 64 : mp_tile<T>() / L2; }
-template <typename T, int L2> constexpr int mp_nt()
-{
-    return mp_tc<T, L2>() * L2 / 4 < 64 ? 64 : (mp_tc<T, L2>() * L2 / 4 > 256 ? 256 : mp_tc<T, L2>() * L2 / 4);
-}
+template <typename T, int L2> constexpr int mp_nt() { return nthreads<L2, mp_tc<T, L2>()>(); }
 
 template <typename T>
 MultiPassGeom multipass_geom(int64_t L)
@@ -648,80 +675,94 @@ template MultiPassGeom multipass_geom<float>(int64_t);
 template <typename T, int L2>
 __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
-    const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
+    int nslots, const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
     const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA)
 {
-    constexpr int TC = mp_tc<T, L2>(), NT = mp_nt<T, L2>();
+    constexpr int TC = mp_tc<T, L2>();
+    using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
     constexpr int L1 = (int)lds_max_len<T>();
     constexpr int64_t L = (int64_t)L1 * L2;
-    __shared__ cpx<T> buf[L2 * TC];
-    const int a1_0 = blockIdx.x * TC;
-    const int sl = blockIdx.y;
-    const int64_t b = blockIdx.z;
+    __shared__ cpx<T> lds[F::LDS];
+    constexpr int tiles = L1 / TC;
+    // tiles fastest: consecutive blocks write adjacent columns of the same rows
+    const int a1_0 = (int)(blockIdx.x % tiles) * TC;
+    const int sl = (int)((blockIdx.x / tiles) % nslots);
+    const int64_t b = blockIdx.x / (tiles * nslots);
     const cpx<T> *es = ell ? ell + (int64_t)(slot0 + sl) * nc : nullptr;
     const cpx<T> *Xb = X ? X + b * nc : nullptr;
-    for (int idx = threadIdx.x; idx < L2 * TC; idx += NT) {
-        const int a2 = idx / TC, c = idx % TC;
+    cpx<T> v[F::E];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+        int a2, c;
+        F::in_pos(e, a2, c);
         const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-        cpx<T> z = {0, 0};
-        if (es) {
-            if (a < n) z = cdiag(es[a], Xb[a]);
-        } else {
-            z = src[a];
-        }
-        buf[idx] = z;
+        if (es) v[e] = a < n ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
+        else v[e] = src[a];
     }
-    __syncthreads();
-    lds_fft<T, L2, TC, NT, false>(buf, twL2);
+    F::forward(v, lds, twL2);
     cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
-    for (int idx = threadIdx.x; idx < L2 * TC; idx += NT) {
-        const int k2 = idx / TC, c = idx % TC;
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+        int k2, c;
+        F::out_pos(e, k2, c);
         const int a1 = a1_0 + c;
-        const int64_t e = (int64_t)a1 * k2; // < L
-        const cpx<T> t = cmul(twA[e % L1], twL2[e / L1]);
-        Ub[a1 + (int64_t)L1 * k2] = cmul(buf[idx], t);
+        const int64_t ex = (int64_t)a1 * k2; // < L
+        const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
+        Ub[a1 + (int64_t)L1 * k2] = cmul(v[e], t);
     }
 }
 
+// the row pass keeps radix 16: two LDS exchanges per transform instead of three
+constexpr int RMAX_ROW = 16;
 template <typename T>
-__global__ __launch_bounds__(256) void k_mp_p2(cpx<T> *U, int L2, const cpx<T> *__restrict__ that_perm,
+constexpr int p2_threads() { return fft_threads((int)lds_max_len<T>(), 1, RMAX_ROW); }
+
+template <typename T>
+__global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, int nsb, const cpx<T> *__restrict__ that_perm,
                                                const cpx<T> *__restrict__ twL1,
                                                const cpx<T> *__restrict__ twA,
                                                const cpx<T> *__restrict__ twL2, int full,
                                                cpx<T> *__restrict__ out, T scale)
 {
     constexpr int L1 = (int)lds_max_len<T>();
-    constexpr int NT = 256, E = L1 / NT;
-    __shared__ cpx<T> buf[L1];
-    const int k2 = blockIdx.x;
+    using F = RegFFT<T, L1, 1, p2_threads<T>(), RMAX_ROW>;
+    __shared__ cpx<T> lds[F::LDS];
+    int k2, sb;
+    xcd_map(blockIdx.x, L2, nsb, k2, sb);
     const int64_t L = (int64_t)L1 * L2;
-    cpx<T> *row = U + (int64_t)blockIdx.y * L + (int64_t)k2 * L1;
+    cpx<T> *row = U + (int64_t)sb * L + (int64_t)k2 * L1;
+    cpx<T> v[F::E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) buf[threadIdx.x + e * NT] = row[threadIdx.x + e * NT];
-    __syncthreads();
-    lds_fft<T, L1, 1, NT, false>(buf, twL1);
+    for (int e = 0; e < F::E; ++e) {
+        int pos, c;
+        F::in_pos(e, pos, c);
+        v[e] = row[pos];
+    }
+    F::forward(v, lds, twL1);
     if (!full) {
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int i = threadIdx.x + e * NT;
-            out[(int64_t)k2 * L1 + i] = cpx<T>{buf[i].x * scale, buf[i].y * scale};
+        for (int e = 0; e < F::E; ++e) {
+            int k1, c;
+            F::out_pos(e, k1, c);
+            out[(int64_t)k2 * L1 + k1] = cpx<T>{v[e].x * scale, v[e].y * scale};
         }
         return;
     }
     const cpx<T> *tp = that_perm + (int64_t)k2 * L1;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = threadIdx.x + e * NT;
-        buf[i] = cmul(buf[i], tp[i]);
+    for (int e = 0; e < F::E; ++e) {
+        int k1, c;
+        F::out_pos(e, k1, c);
+        v[e] = cmul(v[e], tp[k1]);
     }
-    __syncthreads();
-    lds_fft<T, L1, 1, NT, true>(buf, twL1);
+    F::inverse(v, lds, twL1);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int a1 = threadIdx.x + e * NT;
+    for (int e = 0; e < F::E; ++e) {
+        int a1, c;
+        F::in_pos(e, a1, c);
         const int64_t ex = (int64_t)a1 * k2;
         const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
-        row[a1] = cmulc(buf[a1], t);
+        row[a1] = cmulc(v[e], t);
     }
 }
 
@@ -731,16 +772,16 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
     int nslots, int spg, cpx<T> *__restrict__ W, int gofs, int64_t batch,
     const cpx<T> *__restrict__ twL2)
 {
-    constexpr int TC = mp_tc<T, L2>(), NT = mp_nt<T, L2>();
+    constexpr int TC = mp_tc<T, L2>();
+    using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
     constexpr int L1 = (int)lds_max_len<T>();
     constexpr int64_t L = (int64_t)L1 * L2;
-    constexpr int E = L2 * TC / NT;
-    __shared__ cpx<T> buf[L2 * TC];
+    constexpr int E = F::E;
+    __shared__ cpx<T> lds[F::LDS];
     const int a1_0 = blockIdx.x * TC;
     const int g = blockIdx.y;
     const int64_t b = blockIdx.z;
-    const int tid = threadIdx.x;
-    cpx<T> acc[E];
+    cpx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
     const int s1 = min(nslots, (g + 1) * spg);
@@ -748,27 +789,25 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
         const cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int idx = tid + e * NT;
-            const int k2 = idx / TC, c = idx % TC;
-            buf[idx] = Ub[a1_0 + c + (int64_t)L1 * k2];
+            int k2, c;
+            F::out_pos(e, k2, c);
+            v[e] = Ub[a1_0 + c + (int64_t)L1 * k2];
         }
-        __syncthreads();
-        lds_fft<T, L2, TC, NT, true>(buf, twL2);
+        F::inverse(v, lds, twL2);
         const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int idx = tid + e * NT;
-            const int a2 = idx / TC, c = idx % TC;
+            int a2, c;
+            F::in_pos(e, a2, c);
             const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-            if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], buf[idx]));
+            if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], v[e]));
         }
-        __syncthreads();
     }
     cpx<T> *Wg = W + ((int64_t)(gofs + g) * batch + b) * nc;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int idx = tid + e * NT;
-        const int a2 = idx / TC, c = idx % TC;
+        int a2, c;
+        F::in_pos(e, a2, c);
         const int64_t a = a1_0 + c + (int64_t)L1 * a2;
         if (a < n) Wg[a] = acc[e];
     }
@@ -785,10 +824,10 @@ bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, 
 #define THX_P1(LL2)                                                                                   \
     case LL2:                                                                                         \
         if (LL2 * (int64_t)lds_max_len<T>() > (int64_t)1 << 22) return false;                         \
-        k_mp_p1<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>()), (unsigned)nslots, (unsigned)batch), \
+        k_mp_p1<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>() * nslots * batch)),                 \
                           mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,     \
-                                                   slot0, (const cpx<T> *)src, (cpx<T> *)U, batch,    \
-                                                   (const cpx<T> *)twL2, (const cpx<T> *)twA);        \
+                                                   slot0, nslots, (const cpx<T> *)src, (cpx<T> *)U,   \
+                                                   batch, (const cpx<T> *)twL2, (const cpx<T> *)twA); \
         return true;
         THX_L2_CASES(THX_P1)
 #undef THX_P1
@@ -804,8 +843,9 @@ bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, co
                   double scale, hipStream_t s)
 {
     if (g.L1 != lds_max_len<T>() || g.L2 < 2 || g.L2 > 1024) return false;
-    dim3 grid((unsigned)g.L2, (unsigned)(nslots * batch));
-    k_mp_p2<T><<<grid, 256, 0, s>>>((cpx<T> *)U, (int)g.L2, (const cpx<T> *)that_perm,
+    dim3 grid((unsigned)(g.L2 * nslots * batch));
+    k_mp_p2<T><<<grid, p2_threads<T>(), 0, s>>>((cpx<T> *)U, (int)g.L2, (int)(nslots * batch),
+                                                (const cpx<T> *)that_perm,
                                     (const cpx<T> *)twL1, (const cpx<T> *)twA,
                                     (const cpx<T> *)twL2, full ? 1 : 0, (cpx<T> *)out, (T)scale);
     return true;

@@ -527,6 +527,7 @@ void ensure_workspace(thx_plan *p, int64_t batch)
         // slot chunk so that the FFT intermediates stay within ~2 GiB
         const int64_t per = (int64_t)es * p->L * batch;
         int64_t sc = std::max<int64_t>(1, ((int64_t)2 << 30) / per);
+        if (const char *e = getenv("THX_SLOT_CHUNK")) sc = std::max<int64_t>(1, std::min<int64_t>(sc, atoll(e)));
         sc = std::min<int64_t>(sc, std::max(1, p->S));
         p->U_slots = sc;
         p->U = dalloc<char>(per * sc);
