@@ -127,6 +127,37 @@ thx_status thx_lag2lag(const double *alpha, double *beta, int64_t N, int64_t bat
 /* Drop every cached plan (synchronises the device). */
 thx_status thx_cache_clear(void);
 
+/* Mixed-degree batches (Fig. 1 applied to many polynomials; one pivoted
+ * Cholesky per bucket, reused by every member as Sec. 2.1 suggests).
+ * Polynomial i has degree degrees[i] (host array of `count`) and its
+ * coefficients are stored contiguously: alpha[off_i .. off_i + degrees[i]] with
+ * off_i = sum_{m<i} (degrees[m] + 1); beta uses the same layout.  Members are
+ * grouped by FFT length; each group gets one plan at its largest degree (the
+ * Hankel part for degree N is the leading block of the one for a larger
+ * degree, so the factorisation holds for every member).  Degrees up to the
+ * direct crossover (THX_DIRECT_MAX, default 512, or flags) use the O(N^2)
+ * kernel.  All workspace is allocated here; thx_batch_create synchronises
+ * `stream`.  Errors as thx_plan_create, plus THX_INVALID_ARGUMENT for a
+ * negative degree or count. */
+typedef struct thx_batch thx_batch;
+thx_status thx_batch_create(thx_batch **out, thx_kind kind, const double *params, int nparams,
+                            const int64_t *degrees, int64_t count, double tol, thx_precision prec,
+                            uint32_t flags, hipStream_t stream);
+/* Convert every member: device alpha / beta in the layout above.  With
+ * use_graph != 0 the launch sequence is captured once into a hipGraph (on the
+ * batch's own stream; re-captured when alpha or beta change) and replayed on
+ * `stream`; no allocation and no memset node is recorded.  Executions of one
+ * batch must be serialised. */
+thx_status thx_batch_execute(thx_batch *batch, const double *alpha, double *beta, int use_graph,
+                             hipStream_t stream);
+thx_status thx_batch_destroy(thx_batch *batch);
+/* sum of (degree + 1) over the members; number of buckets; per-bucket facts
+ * (fft_length 0 and path 0 for the direct bucket) */
+int64_t thx_batch_coefficients(const thx_batch *batch);
+int32_t thx_batch_buckets(const thx_batch *batch);
+thx_status thx_batch_bucket_info(const thx_batch *batch, int i, int64_t *fft_length, int64_t *members,
+                                 int64_t *max_degree, int32_t *path, int32_t *rank);
+
 /* Lambda table (Sec. 1, definition under eq. (M)):
  * out[i] = Lambda(z0 + i) = Gamma(z0 + i + 1/2) / Gamma(z0 + i + 1), i < count;
  * out is a device pointer.  Exposed for tests of the generator. */

@@ -56,6 +56,14 @@ _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
 _sig("thx_plan_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
 _sig("thx_plan_timings", ctypes.c_int, _vp, _dp, ctypes.POINTER(_i64), ctypes.c_int)
+_sig("thx_batch_create", ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _dp, ctypes.c_int,
+     ctypes.POINTER(_i64), _i64, _dbl, ctypes.c_int, ctypes.c_uint32, _vp)
+_sig("thx_batch_execute", ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp)
+_sig("thx_batch_destroy", ctypes.c_int, _vp)
+_sig("thx_batch_coefficients", _i64, _vp)
+_sig("thx_batch_buckets", _i32, _vp)
+_sig("thx_batch_bucket_info", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+     ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("thx_status_string", ctypes.c_char_p, ctypes.c_int)
 _sig("thx_last_hip_error", ctypes.c_int)
 
@@ -157,6 +165,51 @@ class Plan:
             raise ValueError("alpha and beta must share shape and row stride, unit column stride")
         _check(_lib.thx_execute(self._h, _ptr(a2), _ptr(b2), N, a2.shape[0], a2.stride(0), _stream(stream)),
                "thx_execute")
+        return beta
+
+
+class Batch:
+    """Owns a thx_batch* (thx_batch_create / thx_batch_destroy): mixed degrees, CSR layout."""
+
+    def __init__(self, kind: int, degrees, tol: float, prec: int = FP64, params=(), flags: int = 0,
+                 stream=None):
+        import numpy as np
+        self.degrees = np.ascontiguousarray(degrees, dtype=np.int64)
+        self._h = _vp()
+        arr = (ctypes.c_double * max(1, len(params)))(*params)
+        self.status = _check(_lib.thx_batch_create(
+            ctypes.byref(self._h), kind, arr, len(params),
+            self.degrees.ctypes.data_as(ctypes.POINTER(_i64)), len(self.degrees), tol, prec, flags,
+            _stream(stream)), "thx_batch_create", (0, 3))
+        self.offsets = np.concatenate([[0], np.cumsum(self.degrees + 1)]).astype(np.int64)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.thx_batch_destroy(h)
+            self._h = _vp()
+
+    coefficients = property(lambda self: _lib.thx_batch_coefficients(self._h))
+
+    def buckets(self):
+        out = []
+        for i in range(_lib.thx_batch_buckets(self._h)):
+            L, m, nmax = _i64(), _i64(), _i64()
+            path, rank = _i32(), _i32()
+            _check(_lib.thx_batch_bucket_info(self._h, i, ctypes.byref(L), ctypes.byref(m), ctypes.byref(nmax),
+                                              ctypes.byref(path), ctypes.byref(rank)), "thx_batch_bucket_info")
+            out.append({"L": L.value, "members": m.value, "max_degree": nmax.value, "path": path.value,
+                        "rank": rank.value})
+        return out
+
+    def execute(self, alpha, beta, graph: bool = False, stream=None):
+        _check_tensor(alpha, "alpha")
+        _check_tensor(beta, "beta")
+        n = int(self.offsets[-1])
+        if alpha.numel() < n or beta.numel() < n or not alpha.is_contiguous() or not beta.is_contiguous():
+            raise ValueError("alpha / beta must be contiguous with sum(degree+1) entries")
+        _check(_lib.thx_batch_execute(self._h, _ptr(alpha), _ptr(beta), 1 if graph else 0, _stream(stream)),
+               "thx_batch_execute")
         return beta
 
 

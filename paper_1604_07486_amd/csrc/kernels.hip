@@ -337,13 +337,34 @@ __device__ __forceinline__ double d2_of(const KindDesc &k, int64_t j)
 // a4: pack v = D2 alpha into complex lanes
 // ============================================================================
 // parity-split kinds: lane a holds (v_{2a}, v_{2a+1}); otherwise (v_a, v_a).
+// Per-vector addressing: fixed-degree batches use alpha + b*ld with degree N;
+// mixed-degree batches pass member offsets / degrees (CSR layout).
+struct VecRef {
+    const int64_t *off; // nullable
+    const int64_t *deg; // nullable
+};
+__device__ __forceinline__ void vec_of(const VecRef &v, int64_t b, int64_t ld, int64_t N, int64_t &base,
+                                       int64_t &n)
+{
+    if (v.off) {
+        base = v.off[b];
+        n = v.deg[b];
+    } else {
+        base = b * ld;
+        n = N;
+    }
+}
+
 template <typename T>
-__global__ void k_pack(KindDesc k, const double *alpha, int64_t ld, int64_t N, cpx<T> *X, int64_t nc)
+__global__ void k_pack(KindDesc k, VecRef vr, const double *alpha, int64_t ld, int64_t N0, cpx<T> *X,
+                       int64_t nc)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = blockIdx.y;
     if (a >= nc) return;
-    const double *al = alpha + b * ld;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
+    const double *al = alpha + base;
     double x = 0.0, y = 0.0;
     if (k.parity) {
         const int64_t j0 = 2 * a, j1 = 2 * a + 1;
@@ -356,15 +377,15 @@ __global__ void k_pack(KindDesc k, const double *alpha, int64_t ld, int64_t N, c
 }
 
 template <typename T>
-void launch_pack(const KindDesc &k, const double *alpha, int64_t ld, int64_t N, int64_t batch,
-                 void *X, int64_t nc, hipStream_t s)
+void launch_pack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                 int64_t ld, int64_t N, int64_t batch, void *X, int64_t nc, hipStream_t s)
 {
     const int nt = 256;
     dim3 grid((unsigned)((nc + nt - 1) / nt), (unsigned)batch);
-    k_pack<T><<<grid, nt, 0, s>>>(k, alpha, ld, N, (cpx<T> *)X, nc);
+    k_pack<T><<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, (cpx<T> *)X, nc);
 }
-template void launch_pack<double>(const KindDesc &, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
-template void launch_pack<float>(const KindDesc &, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
+template void launch_pack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
+template void launch_pack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
 
 // ============================================================================
 // a6: sum the partial results, remove the circulant alias, beta = D1 w
@@ -373,15 +394,17 @@ template void launch_pack<float>(const KindDesc &, const double *, int64_t, int6
 // extra term t_{n-1} z_0 at output n-1; it is removed here in double precision:
 //   w_{n-1} -= t_{n-1} v_0 sum_s l~_s[n-1] l~_s[0].
 template <typename T>
-__global__ void k_unpack(KindDesc k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                         const cpx<T> *W, int G, int64_t nc, int64_t batch, int64_t L,
+__global__ void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld, double *beta,
+                         int64_t N0, const cpx<T> *W, int G, int64_t nc, int64_t batch, int64_t L,
                          const double *ell64, int64_t nc_ell, int S, const double *tsym,
                          const double *row0)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = blockIdx.y;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
     if (j > N) return;
-    const double *al = alpha + b * ld;
+    const double *al = alpha + base;
     double w = 0.0;
     if (k.parity) {
         const int64_t a = j >> 1;
@@ -415,32 +438,35 @@ __global__ void k_unpack(KindDesc k, const double *alpha, int64_t ld, double *be
     }
     double out = d1_of(k, j) * w;
     if (row0 && j == 0) out = row0[b];
-    beta[b * ld + j] = out;
+    beta[base + j] = out;
 }
 
 template <typename T>
-void launch_unpack(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                   int64_t batch, const void *Wpart, int G, int64_t nc, int64_t L,
-                   const double *ell64, int64_t nc_ell, int S, const double *tsym,
-                   const double *row0, hipStream_t s)
+void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                   int64_t ld, double *beta, int64_t N, int64_t batch, const void *Wpart, int G,
+                   int64_t nc, int64_t L, const double *ell64, int64_t nc_ell, int S,
+                   const double *tsym, const double *row0, hipStream_t s)
 {
     const int nt = 256;
     dim3 grid((unsigned)((N + 1 + nt - 1) / nt), (unsigned)batch);
-    k_unpack<T><<<grid, nt, 0, s>>>(k, alpha, ld, beta, N, (const cpx<T> *)Wpart, G, nc, batch, L,
-                                    ell64, nc_ell, S, tsym, row0);
+    k_unpack<T><<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, (const cpx<T> *)Wpart, G,
+                                    nc, batch, L, ell64, nc_ell, S, tsym, row0);
 }
-template void launch_unpack<double>(const KindDesc &, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
-template void launch_unpack<float>(const KindDesc &, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
+template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
+template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
 
 // Row 0 of cheb2leg computed directly (Sec. 5.1): the Hankel part is not PSD
 // because of H_00, so rows/columns >= 1 go through the low-rank path and
 //   beta_0 = D1_0 sum_{b >= 0} t_b h(b) D2_{2b} alpha_{2b},  h(0) := 1.
-__global__ __launch_bounds__(256) void k_row0(KindDesc k, const double *alpha, int64_t ld, int64_t N,
-                                              const double *tsym, const double *hk, double *row0)
+__global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                              int64_t N0, const double *tsym, const double *hk,
+                                              double *row0)
 {
     __shared__ double sm[256];
     const int64_t b = blockIdx.x;
-    const double *al = alpha + b * ld;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
+    const double *al = alpha + base;
     double acc = 0.0;
     for (int64_t c = threadIdx.x; 2 * c <= N; c += blockDim.x)
         acc = fma(tsym[c] * hk[c], d2_of(k, 2 * c) * al[2 * c], acc);
@@ -453,23 +479,25 @@ __global__ __launch_bounds__(256) void k_row0(KindDesc k, const double *alpha, i
     if (threadIdx.x == 0) row0[b] = d1_of(k, 0) * sm[0];
 }
 
-void launch_row0_cheb2leg(const KindDesc &k, const double *alpha, int64_t ld, int64_t N,
-                          int64_t batch, const double *tsym, const double *hk, double *row0,
-                          hipStream_t s)
+void launch_row0_cheb2leg(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                          int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
+                          double *row0, hipStream_t s)
 {
-    k_row0<<<(unsigned)batch, 256, 0, s>>>(k, alpha, ld, N, tsym, hk, row0);
+    k_row0<<<(unsigned)batch, 256, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tsym, hk, row0);
 }
 
 // ============================================================================
 // Direct O(N^2) evaluation (Sec. 4 "Direct"): entries generated on the fly
 // ============================================================================
-__global__ void k_direct(KindDesc k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                         const double *tsym, const double *hk)
+__global__ void k_direct(KindDesc k, VecRef vr, const double *alpha, int64_t ld, double *beta,
+                         int64_t N0, const double *tsym, const double *hk)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = blockIdx.y;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
     if (j > N) return;
-    const double *al = alpha + b * ld;
+    const double *al = alpha + base;
     double acc = 0.0;
     if (k.parity) {
         for (int64_t c = j; c <= N; c += 2)
@@ -477,15 +505,29 @@ __global__ void k_direct(KindDesc k, const double *alpha, int64_t ld, double *be
     } else {
         for (int64_t c = j; c <= N; ++c) acc = fma(tsym[c - j] * hk[j + c], d2_of(k, c) * al[c], acc);
     }
-    beta[b * ld + j] = d1_of(k, j) * acc;
+    beta[base + j] = d1_of(k, j) * acc;
 }
 
-void launch_direct(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                   int64_t batch, const double *tsym, const double *hk, hipStream_t s)
+void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                   int64_t ld, double *beta, int64_t N, int64_t batch, const double *tsym,
+                   const double *hk, hipStream_t s)
 {
     const int nt = 128;
     dim3 grid((unsigned)((N + 1 + nt - 1) / nt), (unsigned)batch);
-    k_direct<<<grid, nt, 0, s>>>(k, alpha, ld, beta, N, tsym, hk);
+    k_direct<<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, tsym, hk);
+}
+
+// zero fill (used instead of a memset node so that launch sequences can be graph-captured)
+__global__ void k_zero(double *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+void launch_zero(void *p, int64_t bytes, hipStream_t s)
+{
+    const int64_t count = bytes / 8;
+    if (count <= 0) return;
+    k_zero<<<(unsigned)((count + 255) / 256), 256, 0, s>>>((double *)p, count);
 }
 
 // ============================================================================

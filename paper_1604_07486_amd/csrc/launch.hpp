@@ -86,21 +86,28 @@ void launch_reorder(const double *in, void *out, int64_t L, int64_t L1, int64_t 
                     hipStream_t s);
 
 // ---- a4 / a6: pack and unpack ----------------------------------------------------
+// off / deg (device, per vector, nullable): mixed-degree batches in CSR layout,
+// vector b at alpha + off[b] with degree deg[b]; otherwise alpha + b*ld, degree N
+// (for mixed batches N is the largest degree).
 template <typename T>
-void launch_pack(const KindDesc &k, const double *alpha, int64_t ld, int64_t N, int64_t batch,
-                 void *X /*cpx<T> [batch][nc]*/, int64_t nc, hipStream_t s);
+void launch_pack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                 int64_t ld, int64_t N, int64_t batch, void *X /*cpx<T> [batch][nc]*/, int64_t nc,
+                 hipStream_t s);
 template <typename T>
-void launch_unpack(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                   int64_t batch, const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc,
-                   int64_t L, const double *ell64, int64_t nc_ell, int S, const double *tsym,
+void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                   int64_t ld, double *beta, int64_t N, int64_t batch,
+                   const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc, int64_t L,
+                   const double *ell64, int64_t nc_ell, int S, const double *tsym,
                    const double *row0, hipStream_t s);
-void launch_row0_cheb2leg(const KindDesc &k, const double *alpha, int64_t ld, int64_t N,
-                          int64_t batch, const double *tsym, const double *hk, double *row0,
-                          hipStream_t s);
+void launch_row0_cheb2leg(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                          int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
+                          double *row0, hipStream_t s);
 
 // ---- direct O(N^2) ----------------------------------------------------------------
-void launch_direct(const KindDesc &k, const double *alpha, int64_t ld, double *beta, int64_t N,
-                   int64_t batch, const double *tsym, const double *hk, hipStream_t s);
+void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+                   int64_t ld, double *beta, int64_t N, int64_t batch, const double *tsym,
+                   const double *hk, hipStream_t s);
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
 
 // ---- a5: Toeplitz products ---------------------------------------------------------
 // Largest length handled by one workgroup in LDS, and the row length of the

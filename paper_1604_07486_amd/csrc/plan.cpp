@@ -536,14 +536,14 @@ void ensure_workspace(thx_plan *p, int64_t batch)
 }
 
 template <typename T>
-void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int64_t batch, int64_t ld,
-                 hipStream_t s)
+void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                 int64_t N, int64_t batch, int64_t ld, hipStream_t s)
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
     {
         PhaseTimer t(p, THX_PHASE_PACK, s);
-        launch_pack<T>(p->kd, alpha, ld, N, batch, p->X, p->nc, s);
+        launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, p->X, p->nc, s);
     }
     int G = 0;
     if (p->S > 0) {
@@ -581,21 +581,37 @@ void execute_fft(thx_plan *p, const double *alpha, double *beta, int64_t N, int6
             }
         }
     } else {
-        hip_check(hipMemsetAsync(p->Wp, 0, p->esize() * (size_t)(batch * p->nc), s));
+        launch_zero(p->Wp, (int64_t)(p->esize() * (size_t)(batch * p->nc)), s);
         G = 1;
     }
     const double *row0 = nullptr;
     if (p->kind == THX_CHEB2LEG) {
         PhaseTimer t(p, THX_PHASE_ROW0, s);
-        launch_row0_cheb2leg(p->kd, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
+        launch_row0_cheb2leg(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
         row0 = p->row0;
     }
     {
         PhaseTimer t(p, THX_PHASE_UNPACK, s);
-        launch_unpack<T>(p->kd, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc, p->S,
-                         p->tsym, row0, s);
+        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc,
+                         p->S, p->tsym, row0, s);
     }
     launch_check();
+}
+
+// Launch the whole execution on `s` (no host synchronisation, no allocation
+// once the workspace holds `batch` vectors, no memset nodes: graph-capturable).
+void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s)
+{
+    if (p->path == 0 || degree < 2) {
+        PhaseTimer t(p, THX_PHASE_DIRECT, s);
+        launch_direct(p->kd, off, deg, alpha, ld, beta, degree, batch, p->tsym, p->hk, s);
+        launch_check();
+        return;
+    }
+    ensure_workspace(p, batch);
+    if (p->prec == THX_FP64) execute_fft<double>(p, off, deg, alpha, beta, degree, batch, ld, s);
+    else execute_fft<float>(p, off, deg, alpha, beta, degree, batch, ld, s);
 }
 
 thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int64_t degree, int64_t batch,
@@ -607,15 +623,7 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
     if (batch > 65535) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
     try {
-        if (p->path == 0 || degree < 2) {
-            PhaseTimer t(p, THX_PHASE_DIRECT, s);
-            launch_direct(p->kd, alpha, ld, beta, degree, batch, p->tsym, p->hk, s);
-            launch_check();
-            return THX_OK;
-        }
-        ensure_workspace(p, batch);
-        if (p->prec == THX_FP64) execute_fft<double>(p, alpha, beta, degree, batch, ld, s);
-        else execute_fft<float>(p, alpha, beta, degree, batch, ld, s);
+        execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s);
     } catch (const HipFail &f) {
         g_last_hip_error = (int)f.e;
         return THX_HIP_ERROR;
@@ -656,6 +664,159 @@ thx_status cached_convert(thx_kind kind, const double *params, int np, const dou
         }
     }
     return do_execute(p, alpha, beta, N, batch, N + 1, s);
+}
+
+// ---- mixed-degree batches (CSR layout), one plan per FFT-length bucket ----
+} // namespace
+
+struct thx_batch {
+    struct Bucket {
+        thx_plan *plan = nullptr;
+        int64_t members = 0, Nmax = 0, L = 0;
+        int64_t *d_off = nullptr, *d_deg = nullptr;
+    };
+    int64_t count = 0, total = 0;
+    std::vector<Bucket> buckets;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double *g_alpha = nullptr;
+    double *g_beta = nullptr;
+    ~thx_batch()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (auto &b : buckets) {
+            delete b.plan;
+            dfree(b.d_off);
+            dfree(b.d_deg);
+        }
+    }
+};
+
+namespace {
+
+constexpr int64_t MAX_BUCKET_MEMBERS = 65535; // grid.y limit of the per-vector launches
+
+thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, int nparams, const int64_t *degrees,
+                        int64_t count, double tol, thx_precision prec, uint32_t flags, hipStream_t s)
+{
+    if (!out) return THX_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (count < 0 || (count > 0 && !degrees)) return THX_INVALID_ARGUMENT;
+    for (int64_t i = 0; i < count; ++i)
+        if (degrees[i] < 0) return THX_INVALID_ARGUMENT;
+    double pv[4] = {0, 0, 0, 0};
+    thx_status vs = validate_kind(kind, params, nparams, pv);
+    if (vs != THX_OK) return vs;
+    const bool parity = (kind == THX_LEG2CHEB || kind == THX_CHEB2LEG || kind == THX_ULTRA2ULTRA);
+    thx_batch *b = new (std::nothrow) thx_batch();
+    if (!b) return THX_OUT_OF_MEMORY;
+    b->count = count;
+    // bucket key: 0 for the direct evaluation, else the FFT length
+    std::map<int64_t, std::vector<int64_t>> groups;
+    std::vector<int64_t> off(count);
+    int64_t acc = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        off[i] = acc;
+        acc += degrees[i] + 1;
+        const int64_t N = degrees[i];
+        const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
+                            (!(flags & THX_FLAG_FORCE_FFT) && N <= direct_crossover()) || N < 2;
+        const int64_t nc = parity ? N / 2 + 1 : N + 1;
+        groups[direct ? 0 : std::max<int64_t>(64, next_pow2(2 * nc - 2))].push_back(i);
+    }
+    b->total = acc;
+    thx_status result = THX_OK;
+    try {
+        for (auto &kv : groups) {
+            const std::vector<int64_t> &idx = kv.second;
+            for (size_t c0 = 0; c0 < idx.size(); c0 += MAX_BUCKET_MEMBERS) {
+                const size_t c1 = std::min(idx.size(), c0 + (size_t)MAX_BUCKET_MEMBERS);
+                thx_batch::Bucket bk;
+                std::vector<int64_t> ho, hd;
+                for (size_t m = c0; m < c1; ++m) {
+                    ho.push_back(off[idx[m]]);
+                    hd.push_back(degrees[idx[m]]);
+                    bk.Nmax = std::max(bk.Nmax, degrees[idx[m]]);
+                }
+                bk.members = (int64_t)ho.size();
+                const uint32_t f = kv.first == 0 ? THX_FLAG_FORCE_DIRECT : THX_FLAG_FORCE_FFT;
+                thx_status st = create_plan(&bk.plan, kind, params, nparams, bk.Nmax, tol, prec, f, s);
+                if (st == THX_TOL_NOT_REACHED) result = st;
+                else if (st != THX_OK) {
+                    delete b;
+                    return st;
+                }
+                bk.L = bk.plan->path == 0 ? 0 : bk.plan->L;
+                bk.d_off = dalloc<int64_t>(bk.members);
+                bk.d_deg = dalloc<int64_t>(bk.members);
+                hip_check(hipMemcpyAsync(bk.d_off, ho.data(), sizeof(int64_t) * ho.size(), hipMemcpyHostToDevice, s));
+                hip_check(hipMemcpyAsync(bk.d_deg, hd.data(), sizeof(int64_t) * hd.size(), hipMemcpyHostToDevice, s));
+                if (bk.plan->path != 0) ensure_workspace(bk.plan, bk.members);
+                b->buckets.push_back(bk);
+                hip_check(hipStreamSynchronize(s));
+            }
+        }
+        hip_check(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    } catch (const HipFail &e) {
+        g_last_hip_error = (int)e.e;
+        delete b;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return THX_OUT_OF_MEMORY;
+    }
+    *out = b;
+    return result;
+}
+
+void batch_launch(thx_batch *b, const double *alpha, double *beta, hipStream_t s)
+{
+    for (auto &bk : b->buckets)
+        execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0, s);
+}
+
+thx_status batch_execute(thx_batch *b, const double *alpha, double *beta, int use_graph, hipStream_t s)
+{
+    if (!b) return THX_INVALID_ARGUMENT;
+    if (b->count == 0) return THX_OK;
+    if (!alpha || !beta) return THX_INVALID_ARGUMENT;
+    try {
+        if (!use_graph) {
+            batch_launch(b, alpha, beta, s);
+            return THX_OK;
+        }
+        if (!b->gexec || b->g_alpha != alpha || b->g_beta != beta) {
+            if (b->gexec) {
+                hip_check(hipGraphExecDestroy(b->gexec));
+                b->gexec = nullptr;
+            }
+            // capture on the batch's own stream, replay on the caller's
+            hip_check(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                batch_launch(b, alpha, beta, b->cap_stream);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(b->cap_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamEndCapture(b->cap_stream, &g));
+            hipError_t e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hip_check(e);
+            b->g_alpha = alpha;
+            b->g_beta = beta;
+        }
+        hip_check(hipGraphLaunch(b->gexec, s));
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        return THX_OUT_OF_MEMORY;
+    }
+    return THX_OK;
 }
 
 } // namespace
@@ -807,6 +968,41 @@ thx_status thx_plan_timings(thx_plan *p, double *ms, int64_t *launches, int rese
         if (launches) launches[i] = cnt[i];
     }
     if (reset) p->marks.clear();
+    return THX_OK;
+}
+
+thx_status thx_batch_create(thx_batch **out, thx_kind kind, const double *params, int nparams,
+                            const int64_t *degrees, int64_t count, double tol, thx_precision prec,
+                            uint32_t flags, hipStream_t stream)
+{
+    return batch_create(out, kind, params, nparams, degrees, count, tol, prec, flags, stream);
+}
+
+thx_status thx_batch_execute(thx_batch *batch, const double *alpha, double *beta, int use_graph,
+                             hipStream_t stream)
+{
+    return batch_execute(batch, alpha, beta, use_graph, stream);
+}
+
+thx_status thx_batch_destroy(thx_batch *batch)
+{
+    delete batch;
+    return THX_OK;
+}
+
+int64_t thx_batch_coefficients(const thx_batch *b) { return b ? b->total : -1; }
+int32_t thx_batch_buckets(const thx_batch *b) { return b ? (int32_t)b->buckets.size() : -1; }
+
+thx_status thx_batch_bucket_info(const thx_batch *b, int i, int64_t *fft_length, int64_t *members,
+                                 int64_t *max_degree, int32_t *path, int32_t *rank)
+{
+    if (!b || i < 0 || i >= (int)b->buckets.size()) return THX_INVALID_ARGUMENT;
+    const auto &bk = b->buckets[i];
+    if (fft_length) *fft_length = bk.L;
+    if (members) *members = bk.members;
+    if (max_degree) *max_degree = bk.Nmax;
+    if (path) *path = bk.plan->path;
+    if (rank) *rank = bk.plan->path == 0 ? 0 : bk.plan->S;
     return THX_OK;
 }
 

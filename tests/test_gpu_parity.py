@@ -253,3 +253,73 @@ def test_ultra2ultra(thx, l1, l2, N):
 @pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000)])
 def test_lag2lag(thx, a1, a2, N):
     _check_full(thx, thx.LAG2LAG, N, thx.FP64, params=(a1, a2), flags=thx.FLAG_FORCE_FFT, seed=N, p=1.0)
+
+
+# ---------------------------------------------------------------------------
+# Mixed-degree batches (one factorisation per FFT-length bucket, hipGraph replay)
+# ---------------------------------------------------------------------------
+
+def _batch_inputs(degrees, p, seed):
+    parts = [inputs.coeffs(int(n), p, seed=seed + i) for i, n in enumerate(degrees)]
+    return np.concatenate(parts), parts
+
+
+def _check_batch(thx, degrees, prec, flags=0, graph=False, seed=100):
+    import torch
+    print(f"[case] batch count={len(degrees)} max={int(degrees.max())} prec={prec} flags={flags} graph={graph}",
+          flush=True)
+    flat, parts = _batch_inputs(degrees, 1.0, seed)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64 if prec == thx.FP64 else EPS32, prec, flags=flags)
+    a = _dev(flat)
+    b = torch.full_like(a, float("nan"))
+    bt.execute(a, b, graph=graph)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    worst = 0.0
+    for i, al in enumerate(parts):
+        o = int(bt.offsets[i])
+        ref = oracle.matvec("leg2cheb", al)
+        worst = max(worst, _err(got[o:o + len(al)], ref, al))
+    print(f"  buckets={bt.buckets()}", flush=True)
+    print(f"  worst err={worst:.3e}", flush=True)
+    assert worst < (TOL64 if prec == thx.FP64 else TOL32)
+    assert bt.coefficients == len(flat)
+    return bt
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_mixed_degrees(thx, prec):
+    degrees = inputs.batch_degrees(160, 16, 20000, seed=41)
+    _check_batch(thx, degrees, prec)
+
+
+def test_batch_forced_fft_small_degrees(thx):
+    degrees = inputs.batch_degrees(90, 2, 700, seed=42)
+    _check_batch(thx, degrees, thx.FP64, flags=thx.FLAG_FORCE_FFT)
+
+
+def test_batch_graph_replays_match_eager(thx):
+    import torch
+    degrees = inputs.batch_degrees(64, 16, 9000, seed=43)
+    flat, _ = _batch_inputs(degrees, 1.0, 7)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64, thx.FP64)
+    a = _dev(flat)
+    eager = torch.empty_like(a)
+    bt.execute(a, eager)
+    torch.cuda.synchronize()
+    out = torch.empty_like(a)
+    for rep in range(4):
+        out.fill_(float("nan"))
+        bt.execute(a, out, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        # unrelated eager work on the device between replays
+        junk = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+
+
+def test_batch_empty_and_bad_degree(thx):
+    bt = thx.Batch(thx.LEG2CHEB, np.zeros(0, dtype=np.int64), EPS64)
+    assert bt.coefficients == 0
+    with pytest.raises(thx.ThxError):
+        thx.Batch(thx.LEG2CHEB, np.array([5, -1], dtype=np.int64), EPS64)
