@@ -10,6 +10,9 @@
 // plus the O(N^2) direct evaluation used below the FFT crossover (Sec. 4).
 #include "launch.hpp"
 #include "fft_reg.hpp"
+#ifndef THX_PREFETCH_SYM
+#define THX_PREFETCH_SYM 1
+#endif
 #include "thx_device.hpp"
 #include <math.h>
 
@@ -750,7 +753,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
         const int a1 = a1_0 + c;
         const int64_t ex = (int64_t)a1 * k2; // < L
         const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
-        Ub[a1 + (int64_t)L1 * k2] = cmul(v[e], t);
+        st_stream(Ub + a1 + (int64_t)L1 * k2, cmul(v[e], t));
     }
 }
 
@@ -778,8 +781,21 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
     for (int e = 0; e < F::E; ++e) {
         int pos, c;
         F::in_pos(e, pos, c);
-        v[e] = row[pos];
+        v[e] = ld_stream(row + pos);
     }
+#if THX_PREFETCH_SYM
+    // symbol row read now so that its latency overlaps the forward transform
+    cpx<T> sym[F::E];
+    if (full) {
+        const cpx<T> *tp0 = that_perm + (int64_t)k2 * L1;
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) {
+            int k1, c;
+            F::out_pos(e, k1, c);
+            sym[e] = tp0[k1];
+        }
+    }
+#endif
     F::forward(v, lds, twL1);
     if (!full) {
 #pragma unroll
@@ -790,6 +806,10 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         }
         return;
     }
+#if THX_PREFETCH_SYM
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) v[e] = cmul(v[e], sym[e]);
+#else
     const cpx<T> *tp = that_perm + (int64_t)k2 * L1;
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -797,6 +817,7 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         F::out_pos(e, k1, c);
         v[e] = cmul(v[e], tp[k1]);
     }
+#endif
     F::inverse(v, lds, twL1);
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -804,7 +825,7 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         F::in_pos(e, a1, c);
         const int64_t ex = (int64_t)a1 * k2;
         const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
-        row[a1] = cmulc(v[e], t);
+        st_stream(row + a1, cmulc(v[e], t));
     }
 }
 
@@ -833,7 +854,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
         for (int e = 0; e < E; ++e) {
             int k2, c;
             F::out_pos(e, k2, c);
-            v[e] = Ub[a1_0 + c + (int64_t)L1 * k2];
+            v[e] = ld_stream(Ub + a1_0 + c + (int64_t)L1 * k2);
         }
         F::inverse(v, lds, twL2);
         const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;

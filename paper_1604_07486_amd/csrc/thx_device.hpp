@@ -33,4 +33,34 @@ __device__ __forceinline__ cpx<T> cdiag(cpx<T> d, cpx<T> v) { return {d.x * v.x,
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
+// Streaming (nontemporal) access to data touched once per pass, so that L2
+// keeps the reused tiles (symbol rows, packed input).
+#ifndef THX_NT
+#define THX_NT 1
+#endif
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_stream(const cpx<T> *p)
+{
+    if constexpr (THX_NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+        return cpx<T>{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cpx<T> *p, cpx<T> a)
+{
+    if constexpr (THX_NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 v;
+        v.x = a.x;
+        v.y = a.y;
+        __builtin_nontemporal_store(v, reinterpret_cast<v2 *>(p));
+    } else {
+        *p = a;
+    }
+}
+
 } // namespace thx
