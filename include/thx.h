@@ -45,8 +45,10 @@ typedef enum {
     THX_LEG2CHEB = 0,    /* Legendre -> Chebyshev, eq. (M), Sec. 3                     */
     THX_CHEB2LEG = 1,    /* Chebyshev -> Legendre, eq. (FormulaL), Sec. 5.1            */
     THX_ULTRA2ULTRA = 2, /* C^(l1) -> C^(l2), eq. (UltraSconversion), Sec. 5.2          */
-    THX_JAC2JAC = 3,     /* P^(a,b) -> P^(g,b) (same second parameter), Sec. 5.3 case 2 */
-    THX_LAG2LAG = 4      /* L^(a1) -> L^(a2), Sec. 5.4                                  */
+    THX_JAC2JAC = 3,     /* P^(a,b) -> P^(g,d), Sec. 5.3 (reflection, then case 2)      */
+    THX_LAG2LAG = 4,     /* L^(a1) -> L^(a2), Sec. 5.4                                  */
+    THX_JAC2CHEB = 5,    /* P^(a,b) -> T, Sec. 5.3 (T_k = P_k^(-1/2,-1/2)/P_k^(-1/2,-1/2)(1)) */
+    THX_CHEB2JAC = 6     /* T -> P^(g,d), Sec. 5.3                                     */
 } thx_kind;
 
 typedef enum {
@@ -68,8 +70,12 @@ typedef struct thx_plan thx_plan;
  * open), and transforms the Toeplitz symbol.  The plan may be reused for any
  * number of executions (Sec. 2.1, last paragraph).
  *   params / nparams: kind parameters -- ULTRA2ULTRA (l1, l2) with l1, l2 > 0;
- *   JAC2JAC (a, b, g) with a, b, g > -1, |a - g| < 1 and a + b > -1;
- *   LAG2LAG (a1, a2) with a1, a2 > -1.  LEG2CHEB / CHEB2LEG take none.
+ *   JAC2JAC (a, b, g, d), JAC2CHEB (a, b), CHEB2JAC (g, d), all > -1: a change
+ *   of the second parameter is done first by the reflection
+ *   P_k^(a,b)(-x) = (-1)^k P_k^(b,a)(x), then the first; each of these stages
+ *   must be case 2 of Sec. 5.3 (|first - target| < 1 or = 1, and first +
+ *   second > -1), else THX_UNSUPPORTED;  LAG2LAG (a1, a2) with a1, a2 > -1.
+ *   LEG2CHEB / CHEB2LEG take none.
  *   degree >= 0; 0 < tol < 1; flags: THX_FLAG_*.
  * On success *out owns device memory until thx_plan_destroy.  Errors:
  * THX_INVALID_ARGUMENT (out == NULL, degree < 0, tol outside (0,1), bad params),

@@ -172,6 +172,12 @@ def jac2cheb(alpha, a: float, b: float) -> np.ndarray:
     return y * cheb_norm(x.shape[0] - 1)
 
 
+def cheb2jac(alpha, g: float, d: float) -> np.ndarray:
+    """Coefficients in P^{(g,d)} of sum_k alpha_k T_k: T_k = P_k^{(-1/2,-1/2)} / P_k^{(-1/2,-1/2)}(1)."""
+    x = np.ascontiguousarray(alpha, dtype=np.float64)
+    return jac2jac(x / cheb_norm(x.shape[0] - 1), -0.5, -0.5, g, d)
+
+
 # --------------------------------------------------------------------------
 # Pivoted Cholesky of a PSD matrix given by columns (Sec. 2.1, Fig. 3)
 # --------------------------------------------------------------------------

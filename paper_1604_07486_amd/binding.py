@@ -18,7 +18,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 # enums (include/thx.h)
-LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG = 0, 1, 2, 3, 4
+LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG, JAC2CHEB, CHEB2JAC = 0, 1, 2, 3, 4, 5, 6
 FP64, FP32_BULK = 0, 1
 FLAG_FORCE_DIRECT, FLAG_FORCE_FFT = 1, 2
 PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct"]

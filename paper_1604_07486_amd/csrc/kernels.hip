@@ -102,6 +102,54 @@ void launch_cast(const double *in, float *out, int64_t count, hipStream_t s)
     k_cast<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(in, out, count);
 }
 
+// Jacobi diagonal factors (Sec. 5.3, case 2, second parameter b fixed):
+//   D1_j = (2j + c) Gamma(j + c) / Gamma(j + b + 1)   (j >= 1),
+//   D1_0 = Gamma(c + 1) / Gamma(b + 1)                 (the j = 0 limit, also for c = 0),
+//   D2_k = Gamma(k + b + 1) / Gamma(k + e),            c = g + b + 1, e = a + b + 1,
+// times (-1)^j when the stage is reflected (P_k^{(a,b)}(-x) = (-1)^k P_k^{(b,a)}(x)),
+// and times the Chebyshev normalisation P_j^{(-1/2,-1/2)}(1) = Lambda(j)/sqrt(pi)
+// (cheb = 1, applied to D1) or its reciprocal (cheb = 2, applied to D2).
+__global__ void k_jacobi_diag(double *out, int64_t count, int which, double c, GammaRatio r1, GammaRatio r0,
+                              GammaRatio lam, int reflect, int cheb)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const double z = (double)j;
+    double v;
+    if (which == 1) v = (j == 0) ? gamma_ratio(0.0, r0) : (2.0 * z + c) * gamma_ratio(z, r1);
+    else v = gamma_ratio(z, r1);
+    if (reflect && (j & 1)) v = -v;
+    const double rsqrtpi = 0.56418958354775628694807945156077259; // 1/sqrt(pi)
+    if (cheb == 1) v *= gamma_ratio(z, lam) * rsqrtpi;
+    else if (cheb == 2) v /= gamma_ratio(z, lam) * rsqrtpi;
+    out[j] = v;
+}
+
+void launch_jacobi_diag(double *out, int64_t count, int which, double a, double b, double g, int reflect,
+                        int cheb, hipStream_t s)
+{
+    const double c = g + b + 1.0, e = a + b + 1.0;
+    const GammaRatio r1 = which == 1 ? make_gamma_ratio(c, b + 1.0) : make_gamma_ratio(b + 1.0, e);
+    const GammaRatio r0 = make_gamma_ratio(c + 1.0, b + 1.0);
+    const GammaRatio lam = make_gamma_ratio(0.5, 1.0);
+    const int nt = 256;
+    k_jacobi_diag<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(out, count, which, c, r1, r0, lam,
+                                                                   reflect, cheb);
+}
+
+// Jacobi case 3 (a + b <= -1): H_00 and D2_0 hold a 0 * infinity limit; the
+// (0, 0) entry of any conversion matrix is 1 (P_0 = 1 in every basis), so set
+// h(0) = 1 and D2_0 = 1 / D1_0.
+__global__ void k_case3_origin(double *hk, const double *d1, double *d2)
+{
+    hk[0] = 1.0;
+    d2[0] = 1.0 / d1[0];
+}
+void launch_case3_origin(double *hk, const double *d1, double *d2, hipStream_t s)
+{
+    k_case3_origin<<<1, 1, 0, s>>>(hk, d1, d2);
+}
+
 __global__ void k_set_value(double *p, double v) { *p = v; }
 void launch_set_value(double *p, double v, hipStream_t s) { k_set_value<<<1, 1, 0, s>>>(p, v); }
 
@@ -458,9 +506,11 @@ void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, co
 template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
 template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
 
-// Row 0 of cheb2leg computed directly (Sec. 5.1): the Hankel part is not PSD
-// because of H_00, so rows/columns >= 1 go through the low-rank path and
-//   beta_0 = D1_0 sum_{b >= 0} t_b h(b) D2_{2b} alpha_{2b},  h(0) := 1.
+// Row 0 computed directly when the Hankel part is PSD only on indices >= 1
+// (cheb2leg, Sec. 5.1; Jacobi case 3, Sec. 5.3): rows/columns >= 1 go through
+// the low-rank path and
+//   beta_0 = D1_0 sum_k t_k h(k) D2_k alpha_k   (k even only for parity kinds),
+// with the (0, 0) entry set through h(0), D2_0 by the plan.
 __global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
                                               int64_t N0, const double *tsym, const double *hk,
                                               double *row0)
@@ -471,8 +521,13 @@ __global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const doubl
     vec_of(vr, b, ld, N0, base, N);
     const double *al = alpha + base;
     double acc = 0.0;
-    for (int64_t c = threadIdx.x; 2 * c <= N; c += blockDim.x)
-        acc = fma(tsym[c] * hk[c], d2_of(k, 2 * c) * al[2 * c], acc);
+    if (k.parity) {
+        for (int64_t c = threadIdx.x; 2 * c <= N; c += blockDim.x)
+            acc = fma(tsym[c] * hk[c], d2_of(k, 2 * c) * al[2 * c], acc);
+    } else {
+        for (int64_t c = threadIdx.x; c <= N; c += blockDim.x)
+            acc = fma(tsym[c] * hk[c], d2_of(k, c) * al[c], acc);
+    }
     sm[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -482,7 +537,7 @@ __global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const doubl
     if (threadIdx.x == 0) row0[b] = d1_of(k, 0) * sm[0];
 }
 
-void launch_row0_cheb2leg(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                           int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
                           double *row0, hipStream_t s)
 {
@@ -502,11 +557,12 @@ __global__ void k_direct(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
     if (j > N) return;
     const double *al = alpha + base;
     double acc = 0.0;
+    const int64_t cend = k.band >= 0 ? min(N, j + k.band) : N;
     if (k.parity) {
-        for (int64_t c = j; c <= N; c += 2)
+        for (int64_t c = j; c <= cend; c += 2)
             acc = fma(tsym[(c - j) >> 1] * hk[(j + c) >> 1], d2_of(k, c) * al[c], acc);
     } else {
-        for (int64_t c = j; c <= N; ++c) acc = fma(tsym[c - j] * hk[j + c], d2_of(k, c) * al[c], acc);
+        for (int64_t c = j; c <= cend; ++c) acc = fma(tsym[c - j] * hk[j + c], d2_of(k, c) * al[c], acc);
     }
     beta[base + j] = d1_of(k, j) * acc;
 }

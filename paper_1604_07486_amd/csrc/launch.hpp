@@ -27,6 +27,7 @@ struct KindDesc {
     double p[4];  // kind parameters
     const double *d1tab; // optional D1 table (length >= N+1), else closed form
     const double *d2tab; // optional D2 table
+    int64_t band;        // >= 0: A_jk = 0 for k - j > band (identity stages); -1: full
 };
 
 // Device state of the pivoted Cholesky (two independent parts at most).
@@ -50,6 +51,10 @@ void launch_gamma_ratio(double *out, int64_t count, double z0, const GammaRatio 
 void launch_twiddles(double *tw64, float *tw32, int64_t M, int64_t count, hipStream_t s);
 void launch_cast(const double *in, float *out, int64_t count, hipStream_t s);
 void launch_set_value(double *p, double v, hipStream_t s);
+void launch_case3_origin(double *hk, const double *d1, double *d2, hipStream_t s);
+// D1 (which = 1) or D2 (which = 2) of a Jacobi stage (a, b) -> (g, b), see kernels.hip
+void launch_jacobi_diag(double *out, int64_t count, int which, double a, double b, double g, int reflect,
+                        int cheb, hipStream_t s);
 
 // ---- a2: pivoted Cholesky ------------------------------------------------------
 // parts: 2 for parity-split kinds (even/odd, generator h_q(s) = hk[s + q]),
@@ -99,7 +104,7 @@ void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, co
                    const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc, int64_t L,
                    const double *ell64, int64_t nc_ell, int S, const double *tsym,
                    const double *row0, hipStream_t s);
-void launch_row0_cheb2leg(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
+void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                           int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
                           double *row0, hipStream_t s);
 

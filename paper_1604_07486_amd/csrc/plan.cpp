@@ -51,12 +51,32 @@ inline void dfree(void *p)
     if (p) (void)hipFree(p);
 }
 
+// (dl)_m / m! for m = 0..nt-1 when dl = -n is a negative integer: (-1)^m C(n, m)
+// for m <= n and zero beyond (the integer-difference, banded case).  Returns n.
+int64_t fill_banded_symbol(double *tsym_dev, int64_t nt, double dl, hipStream_t s);
+
 int64_t next_pow2(int64_t x)
 {
     int64_t p = 1;
     while (p < x) p <<= 1;
     return p;
 }
+
+int64_t fill_banded_symbol(double *tsym_dev, int64_t nt, double dl, hipStream_t s)
+{
+    const int64_t n = (int64_t)(-dl);
+    std::vector<double> h((size_t)nt, 0.0);
+    double c = 1.0; // C(n, m)
+    for (int64_t m = 0; m <= n && m < nt; ++m) {
+        h[(size_t)m] = (m & 1) ? -c : c;
+        c = c * (double)(n - m) / (double)(m + 1);
+    }
+    hip_check(hipMemcpyAsync(tsym_dev, h.data(), sizeof(double) * (size_t)nt, hipMemcpyHostToDevice, s));
+    hip_check(hipStreamSynchronize(s));
+    return n;
+}
+
+inline bool neg_integer(double x) { return x < 0 && x == std::floor(x); }
 
 } // namespace
 
@@ -90,8 +110,23 @@ GammaRatio thx::make_gamma_ratio(double a, double b)
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------
+// One Jacobi conversion stage (a, b) -> (g, b) with the second parameter fixed
+// (Sec. 5.3, case 2); `reflect` realises a change of the second parameter as
+// R A R, `cheb` folds the Chebyshev normalisation into D1 (1) or D2 (2).
+struct JacStage {
+    double a = 0, b = 0, g = 0;
+    int reflect = 0, cheb = 0;
+};
+inline bool jac_case3(const JacStage &J) { return !(J.a + J.b > -1.0); }
+
 struct thx_plan {
     thx_kind kind = THX_LEG2CHEB;
+    bool is_jac_stage = false;
+    bool row0_direct = false; // row 0 by a direct dot product (Hankel PSD on indices >= 1 only)
+    JacStage jac;
+    thx_plan *next = nullptr; // second stage of a two-stage conversion
+    double *tmp = nullptr;    // intermediate coefficients between the stages
+    int64_t tmp_elems = 0;
     double params[4] = {0, 0, 0, 0};
     int64_t N = 0;
     double tol = 0;
@@ -165,6 +200,8 @@ struct thx_plan {
         delete[] pivots[0];
         delete[] pivots[1];
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        dfree(tmp);
+        delete next;
     }
 };
 
@@ -236,6 +273,30 @@ double *symbol_spectrum64(thx_plan *p, hipStream_t s)
 void build_tables(thx_plan *p, hipStream_t s)
 {
     const int64_t nt = p->nc, nh = 2 * p->nc + 2;
+    if (p->is_jac_stage) {
+        // Sec. 5.3 case 2 with b fixed: t_m = (a-g)_m/m!, H_s = Gamma(s+e)/Gamma(s+c+1),
+        // e = a+b+1, c = g+b+1; D1, D2 from k_jacobi_diag
+        const JacStage &J = p->jac;
+        const double dl = J.a - J.g, e = J.a + J.b + 1.0, c = J.g + J.b + 1.0;
+        p->tsym = dalloc<double>(nt);
+        p->hk = dalloc<double>(nh);
+        p->d1tab = dalloc<double>(p->N + 1);
+        p->d2tab = dalloc<double>(p->N + 1);
+        if (dl == 0.0 || neg_integer(dl)) {
+            // identity or integer step (case 1): the Toeplitz factor is banded
+            p->kd.band = fill_banded_symbol(p->tsym, nt, dl, s);
+        } else {
+            launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
+        }
+        launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(e, c + 1.0), 1.0, s);
+        launch_jacobi_diag(p->d1tab, p->N + 1, 1, J.a, J.b, J.g, J.reflect, J.cheb == 1 ? 1 : 0, s);
+        launch_jacobi_diag(p->d2tab, p->N + 1, 2, J.a, J.b, J.g, J.reflect, J.cheb == 2 ? 2 : 0, s);
+        if (jac_case3(J)) launch_case3_origin(p->hk, p->d1tab, p->d2tab, s);
+        p->kd.d1tab = p->d1tab;
+        p->kd.d2tab = p->d2tab;
+        launch_check();
+        return;
+    }
     switch (p->kind) {
     case THX_LEG2CHEB: {
         // T_jk = Lambda((k-j)/2), H_jk = Lambda((j+k)/2): one table Lambda(m)
@@ -258,10 +319,10 @@ void build_tables(thx_plan *p, hipStream_t s)
         const double l1 = p->params[0], l2 = p->params[1], dl = l1 - l2;
         p->tsym = dalloc<double>(nt);
         p->hk = dalloc<double>(nh);
-        // t_m = (dl)_m / m! = Gamma(m + dl) / (Gamma(dl) Gamma(m + 1)); dl = 0 is the identity
-        if (dl == 0.0) {
-            hip_check(hipMemsetAsync(p->tsym, 0, sizeof(double) * nt, s));
-            launch_set_value(p->tsym, 1.0, s);
+        // t_m = (dl)_m / m! = Gamma(m + dl) / (Gamma(dl) Gamma(m + 1)); dl = 0 is the
+        // identity and a negative integer dl the banded integer step (case 1)
+        if (dl == 0.0 || neg_integer(dl)) {
+            p->kd.band = 2 * fill_banded_symbol(p->tsym, nt, dl, s); // in units of k - j
         } else {
             launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
         }
@@ -274,7 +335,8 @@ void build_tables(thx_plan *p, hipStream_t s)
         const double dl = p->params[0] - p->params[1];
         p->tsym = dalloc<double>(nt);
         p->hk = dalloc<double>(nh);
-        launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
+        if (dl == 0.0 || neg_integer(dl)) p->kd.band = fill_banded_symbol(p->tsym, nt, dl, s);
+        else launch_gamma_ratio(p->tsym, nt, 0.0, make_gamma_ratio(dl, 1.0), 1.0 / std::tgamma(dl), s);
         // Hankel part = all ones (Sec. 5.4): Gamma(s+1)/Gamma(s+1)
         launch_gamma_ratio(p->hk, nh, 0.0, make_gamma_ratio(1.0, 1.0), 1.0, s);
         break;
@@ -402,21 +464,79 @@ thx_status validate_kind(thx_kind kind, const double *params, int nparams, doubl
         // Hankel part PSD needs l1 - l2 <= 1 (Sec. 5.2, case 2); integer differences
         // other than 0 and 1 are the banded case 1
         if (dl > 1.0) return THX_UNSUPPORTED;
-        if (dl < 0 && dl == std::floor(dl)) return THX_UNSUPPORTED;
+        return THX_OK;
+    }
+    case THX_JAC2JAC:
+    case THX_JAC2CHEB:
+    case THX_CHEB2JAC: {
+        const int np = kind == THX_JAC2JAC ? 4 : 2;
+        if (!need(np)) return THX_INVALID_ARGUMENT;
+        for (int i = 0; i < np; ++i) {
+            if (!(params[i] > -1) || !std::isfinite(params[i])) return THX_INVALID_ARGUMENT;
+            out[i] = params[i];
+        }
         return THX_OK;
     }
     case THX_LAG2LAG: {
         if (!need(2)) return THX_INVALID_ARGUMENT;
         const double a1 = params[0], a2 = params[1];
         if (!(a1 > -1) || !(a2 > -1) || !std::isfinite(a1) || !std::isfinite(a2)) return THX_INVALID_ARGUMENT;
-        const double dl = a1 - a2;
-        if (dl <= 0 && dl == std::floor(dl)) return THX_UNSUPPORTED;
         out[0] = a1;
         out[1] = a2;
         return THX_OK;
     }
     default: return THX_UNSUPPORTED;
     }
+}
+
+thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const JacStage *jac, int64_t degree,
+                         double tol, thx_precision prec, uint32_t flags, hipStream_t s);
+
+// Jacobi conversions (Sec. 5.3): a change of the second parameter b -> d first
+// (reflected stage), then of the first a -> g; each stage must be case 2
+// (|a - g| < 1 or a - g = 1, and a + b > -1 so that the Hankel part is PSD).
+thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_t degree, double tol,
+                         thx_precision prec, uint32_t flags, hipStream_t s)
+{
+    double a, b, g, d;
+    int cheb_first = 0, cheb_last = 0;
+    if (kind == THX_JAC2JAC) {
+        a = pv[0], b = pv[1], g = pv[2], d = pv[3];
+    } else if (kind == THX_JAC2CHEB) {
+        a = pv[0], b = pv[1], g = -0.5, d = -0.5;
+        cheb_last = 1;
+    } else {
+        a = -0.5, b = -0.5, g = pv[0], d = pv[1];
+        cheb_first = 2;
+    }
+    std::vector<JacStage> st;
+    if (b != d) st.push_back(JacStage{b, a, d, 1, 0}); // (b, a) -> (d, a), reflected
+    if (a != g || st.empty()) st.push_back(JacStage{a, d, g, 0, 0});
+    st.front().cheb = cheb_first ? cheb_first : st.front().cheb;
+    if (cheb_last) {
+        if (cheb_first == 0 && st.size() == 1 && st[0].cheb == 0) st[0].cheb = 1;
+        else st.back().cheb = 1;
+    }
+    for (const JacStage &J : st) {
+        // case 3 (a + b <= -1) runs with row 0 computed directly, case 1 (integer
+        // steps down) with the banded Toeplitz factor; case 4 (first parameter
+        // moving by more than 1) is not built
+        if (J.a - J.g > 1.0) return THX_UNSUPPORTED;
+    }
+    thx_plan *first = nullptr, *second = nullptr;
+    thx_status r = create_single(&first, kind, pv, &st[0], degree, tol, prec, flags, s);
+    if (r != THX_OK && r != THX_TOL_NOT_REACHED) return r;
+    if (st.size() > 1) {
+        thx_status r2 = create_single(&second, kind, pv, &st[1], degree, tol, prec, flags, s);
+        if (r2 != THX_OK && r2 != THX_TOL_NOT_REACHED) {
+            delete first;
+            return r2;
+        }
+        if (r2 == THX_TOL_NOT_REACHED) r = r2;
+        first->next = second;
+    }
+    *out = first;
+    return r;
 }
 
 thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
@@ -429,15 +549,28 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
     double pv[4] = {0, 0, 0, 0};
     thx_status vs = validate_kind(kind, params, nparams, pv);
     if (vs != THX_OK) return vs;
+    if (kind == THX_JAC2JAC || kind == THX_JAC2CHEB || kind == THX_CHEB2JAC)
+        return create_jacobi(out, kind, pv, degree, tol, prec, flags, s);
+    return create_single(out, kind, pv, nullptr, degree, tol, prec, flags, s);
+}
+
+thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const JacStage *jac, int64_t degree,
+                         double tol, thx_precision prec, uint32_t flags, hipStream_t s)
+{
     thx_plan *p = new (std::nothrow) thx_plan();
     if (!p) return THX_OUT_OF_MEMORY;
+    p->kd.band = -1;
+    if (jac) {
+        p->is_jac_stage = true;
+        p->jac = *jac;
+    }
     p->kind = kind;
-    std::memcpy(p->params, pv, sizeof(pv));
+    std::memcpy(p->params, pv, sizeof(p->params));
     p->N = degree;
     p->tol = tol;
     p->prec = prec;
     p->flags = flags;
-    p->kd.kind = (int)kind;
+    p->kd.kind = jac ? (int)THX_JAC2JAC : (int)kind;
     p->kd.parity = (kind == THX_LEG2CHEB || kind == THX_CHEB2LEG || kind == THX_ULTRA2ULTRA) ? 1 : 0;
     for (int i = 0; i < 4; ++i) p->kd.p[i] = pv[i];
     if (p->kd.parity) {
@@ -451,13 +584,14 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
         p->parts = 1;
         p->nc = degree + 1;
         p->npart[0] = degree + 1;
+        p->a0[0] = (jac && jac_case3(*jac)) ? 1 : 0;
     }
+    p->row0_direct = (kind == THX_CHEB2LEG) || (jac && jac_case3(*jac));
     try {
         build_tables(p, s);
         const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
                             (!(flags & THX_FLAG_FORCE_FFT) && degree <= direct_crossover()) ||
-                            degree < 2 ||
-                            (kind == THX_ULTRA2ULTRA && p->params[0] == p->params[1]);
+                            degree < 2 || p->kd.band >= 0;
         if (direct) {
             p->path = 0;
             hip_check(hipStreamSynchronize(s));
@@ -585,9 +719,9 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
         G = 1;
     }
     const double *row0 = nullptr;
-    if (p->kind == THX_CHEB2LEG) {
+    if (p->row0_direct) {
         PhaseTimer t(p, THX_PHASE_ROW0, s);
-        launch_row0_cheb2leg(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
+        launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
         row0 = p->row0;
     }
     {
@@ -598,10 +732,37 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     launch_check();
 }
 
+void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s);
+
+void ensure_tmp(thx_plan *p, int64_t elems)
+{
+    if (elems <= p->tmp_elems) return;
+    dfree(p->tmp);
+    p->tmp = nullptr;
+    p->tmp_elems = 0;
+    p->tmp = dalloc<double>(elems);
+    p->tmp_elems = elems;
+}
+
 // Launch the whole execution on `s` (no host synchronisation, no allocation
-// once the workspace holds `batch` vectors, no memset nodes: graph-capturable).
+// once the workspace is sized, no memset nodes: graph-capturable).  Two-stage
+// plans go through the plan's intermediate buffer of `tmp_elems` doubles
+// (laid out like alpha).
 void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s)
+                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems)
+{
+    if (!p->next) {
+        execute_stage(p, off, deg, alpha, beta, degree, batch, ld, s);
+        return;
+    }
+    ensure_tmp(p, tmp_elems);
+    execute_stage(p, off, deg, alpha, p->tmp, degree, batch, ld, s);
+    execute_stage(p->next, off, deg, p->tmp, beta, degree, batch, ld, s);
+}
+
+void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s)
 {
     if (p->path == 0 || degree < 2) {
         PhaseTimer t(p, THX_PHASE_DIRECT, s);
@@ -623,7 +784,7 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
     if (batch > 65535) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
     try {
-        execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s);
+        execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s, batch * ld);
     } catch (const HipFail &f) {
         g_last_hip_error = (int)f.e;
         return THX_HIP_ERROR;
@@ -752,7 +913,9 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                 bk.d_deg = dalloc<int64_t>(bk.members);
                 hip_check(hipMemcpyAsync(bk.d_off, ho.data(), sizeof(int64_t) * ho.size(), hipMemcpyHostToDevice, s));
                 hip_check(hipMemcpyAsync(bk.d_deg, hd.data(), sizeof(int64_t) * hd.size(), hipMemcpyHostToDevice, s));
-                if (bk.plan->path != 0) ensure_workspace(bk.plan, bk.members);
+                for (thx_plan *q = bk.plan; q; q = q->next)
+                    if (q->path != 0) ensure_workspace(q, bk.members);
+                if (bk.plan->next) ensure_tmp(bk.plan, acc);
                 b->buckets.push_back(bk);
                 hip_check(hipStreamSynchronize(s));
             }
@@ -773,7 +936,7 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
 void batch_launch(thx_batch *b, const double *alpha, double *beta, hipStream_t s)
 {
     for (auto &bk : b->buckets)
-        execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0, s);
+        execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0, s, b->total);
 }
 
 thx_status batch_execute(thx_batch *b, const double *alpha, double *beta, int use_graph, hipStream_t s)
@@ -844,13 +1007,25 @@ thx_status thx_plan_destroy(thx_plan *plan)
     return THX_OK;
 }
 
-int32_t thx_plan_rank(const thx_plan *p) { return p ? (p->path == 0 ? 0 : p->S) : -1; }
+int32_t thx_plan_rank(const thx_plan *p)
+{
+    if (!p) return -1;
+    int32_t r = 0;
+    for (const thx_plan *q = p; q; q = q->next) r = std::max<int32_t>(r, q->path == 0 ? 0 : q->S);
+    return r;
+}
 int32_t thx_plan_rank_part(const thx_plan *p, int part)
 {
     if (!p || part < 0 || part >= p->parts || p->path == 0) return -1;
     return p->K[part];
 }
-int64_t thx_plan_fft_length(const thx_plan *p) { return p ? (p->path == 0 ? 0 : p->L) : -1; }
+int64_t thx_plan_fft_length(const thx_plan *p)
+{
+    if (!p) return -1;
+    int64_t L = 0;
+    for (const thx_plan *q = p; q; q = q->next) L = std::max<int64_t>(L, q->path == 0 ? 0 : q->L);
+    return L;
+}
 int32_t thx_plan_path(const thx_plan *p) { return p ? p->path : -1; }
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {

@@ -244,13 +244,13 @@ def test_cheb2leg_fft_fp32(thx, N):
 
 
 @pytest.mark.parametrize("l1,l2,N", [(1.5, 0.5, 255), (1.5, 0.5, 3000), (0.75, 0.25, 1500), (1.0, 0.5, 9000),
-                                     (0.5, 1.25, 2000), (0.3, 0.3, 50)])
+                                     (0.5, 1.25, 2000), (0.3, 0.3, 50), (0.5, 2.5, 4000)])
 def test_ultra2ultra(thx, l1, l2, N):
     _check_full(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(l1, l2), flags=thx.FLAG_FORCE_FFT, seed=N,
                 scale_bar=True)
 
 
-@pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000)])
+@pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000), (-0.5, 1.5, 2000)])
 def test_lag2lag(thx, a1, a2, N):
     _check_full(thx, thx.LAG2LAG, N, thx.FP64, params=(a1, a2), flags=thx.FLAG_FORCE_FFT, seed=N, p=1.0)
 
@@ -323,3 +323,109 @@ def test_batch_empty_and_bad_degree(thx):
     assert bt.coefficients == 0
     with pytest.raises(thx.ThxError):
         thx.Batch(thx.LEG2CHEB, np.array([5, -1], dtype=np.int64), EPS64)
+
+
+# ---------------------------------------------------------------------------
+# Jacobi conversions (Sec. 5.3): case 2 stages, reflection, Chebyshev ends
+# ---------------------------------------------------------------------------
+
+def _jac_ref(kind, alpha, params):
+    if kind == 3:
+        return oracle.jac2jac(alpha, *params)
+    if kind == 5:
+        return oracle.jac2cheb(alpha, *params)
+    return oracle.cheb2jac(alpha, *params)
+
+
+def _jac_scale(kind, N, params):
+    """Bound on the entries of the stage matrices: the bar scales with it (see _check_full)."""
+    if kind == 3:
+        a, b, g, d = params
+    elif kind == 5:
+        (a, b), (g, d) = params, (-0.5, -0.5)
+    else:
+        (a, b), (g, d) = (-0.5, -0.5), params
+    s = 1.0
+    if b != d:
+        s *= max(1.0, oracle.absmax("jac2jac_b", min(N, 400), (b, a, d)))
+    if a != g:
+        s *= max(1.0, oracle.absmax("jac2jac_b", min(N, 400), (a, d, g)))
+    if kind == 6:
+        s *= float(np.sqrt(np.pi) / oracle.lambda_table(N)[-1])
+    return s
+
+
+@pytest.mark.parametrize("kind,params,N,prec,flags", [
+    (3, (0.0, 0.5 ** 0.5, -0.25, 0.5 ** 0.5), 100, 0, 2),     # Fig. 7 pair
+    (3, (0.0, 0.5 ** 0.5, -0.25, 0.5 ** 0.5), 2000, 0, 2),
+    (3, (0.0, 0.5 ** 0.5, -0.25, 0.5 ** 0.5), 6000, 0, 0),
+    (3, (0.5, -0.25, -0.5, -0.5), 1500, 0, 2),                # reflection + integer step
+    (5, (0.5, -0.25), 255, 0, 0),                              # config 5, direct
+    (5, (0.5, -0.25), 255, 0, 2),                              # config 5, FFT
+    (5, (0.5, -0.25), 3000, 0, 2),
+    (5, (0.5, -0.25), 3000, 1, 2),
+    (6, (0.5, -0.25), 1200, 0, 2),
+    (5, (-0.5, -0.5), 700, 0, 2),                              # identity stage + normalisation
+    (3, (-0.5, -0.75, -0.25, -0.75), 900, 0, 2),               # case 3: a + b <= -1
+    (6, (-0.25, 0.5), 2500, 0, 0),
+    (3, (-0.5, 0.3, 1.5, 0.3), 1100, 0, 0),                    # case 1: integer step up (banded)
+])
+def test_jacobi(thx, kind, params, N, prec, flags):
+    import torch
+    print(f"[case] jacobi kind={kind} params={params} N={N} prec={prec} flags={flags}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=N + kind)
+    plan = thx.Plan(kind, N, EPS64 if prec == 0 else EPS32, prec, params=params, flags=flags)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    ref = _jac_ref(kind, alpha, params)
+    err = _err(got, ref, alpha)
+    scale = _jac_scale(kind, N, params)
+    print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} err={err:.3e} scale={scale:.3g}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < (TOL64 if prec == 0 else TOL32) * scale
+
+
+def _cheb_eval(c, x):
+    """Clenshaw for sum c_k T_k(x) (float64)."""
+    b1 = np.zeros_like(x)
+    b2 = np.zeros_like(x)
+    for ck in c[:0:-1]:
+        b1, b2 = 2 * x * b1 - b2 + ck, b1
+    return x * b1 - b2 + c[0]
+
+
+def _jacobi_eval(c, x, a, b):
+    """sum c_k P_k^{(a,b)}(x) by the three-term recurrence (float64)."""
+    p0 = np.ones_like(x)
+    p1 = (a + 1) + (a + b + 2) * (x - 1) / 2
+    s = c[0] * p0 + c[1] * p1
+    for n in range(1, len(c) - 1):
+        s2 = 2 * n + a + b
+        p2 = ((s2 + 1) * ((s2 + 2) * s2 * x + a * a - b * b) * p1
+              - 2 * (n + a) * (n + b) * (s2 + 2) * p0) / (2 * (n + 1) * (n + a + b + 1) * s2)
+        s = s + c[n + 1] * p2
+        p0, p1 = p1, p2
+    return s
+
+
+def test_jac2cheb_full_size_polynomial_identity(thx):
+    # config 5 large member: degree 2^18; the expansion in T_k must represent the
+    # same polynomial (a property that holds at any size; |dp| <= ||d beta||_1)
+    import torch
+    N = 1 << 18
+    alpha = inputs.coeffs(N, 1.0, seed=18)
+    plan = thx.Plan(thx.JAC2CHEB, N, EPS64, thx.FP64, params=(0.5, -0.25))
+    a = _dev(alpha)
+    b = torch.empty_like(a)
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    beta = b.cpu().numpy()
+    x = inputs.points(32, seed=3) * 0.999
+    lhs = _jacobi_eval(alpha, x, 0.5, -0.25)
+    rhs = _cheb_eval(beta, x)
+    err = float(np.max(np.abs(lhs - rhs)) / np.sum(np.abs(alpha)))
+    print(f"  K={plan.rank} L={plan.fft_length} identity err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(beta)) and err < 1e-9

@@ -116,7 +116,8 @@ def test_ultra_exact(l1, l2):
 @pytest.mark.parametrize("a,b,g", [(F(1, 2), F(-1, 4), F(-1, 2)), (F(0), F(1, 2), F(-1, 4)),
                                    (F(1, 2), F(-1, 2), F(-1, 2)), (F(-1, 4), F(1, 2), F(1, 2)),
                                    (F(-1, 2), F(-3, 4), F(-3, 4)), (F(-1, 2), F(-1, 2), F(0)),
-                                   (F(2), F(0), F(1, 2))])
+                                   (F(2), F(0), F(1, 2)), (F(-1, 2), F(-1, 4), F(1, 2)),
+                                   (F(1, 3), F(1, 5), F(7, 3))])
 def test_jacobi_same_beta_exact(a, b, g):
     A = eb.conversion(eb.basis("jacobi", N_EXACT, (a, b)), eb.basis("jacobi", N_EXACT, (g, b)), N_EXACT)
     got = oracle.dense("jac2jac_b", N_EXACT, (float(a), float(b), float(g)))
@@ -144,6 +145,17 @@ def test_jac2cheb_exact():
         e = np.zeros(N + 1)
         e[k] = 1.0
         assert np.max(np.abs(oracle.jac2cheb(e, float(a), float(b)) - Af[:, k])) < 1e-14
+
+
+def test_cheb2jac_exact():
+    g, d = F(1, 2), F(-1, 4)
+    N = 10
+    A = eb.conversion(eb.basis("cheb", N), eb.basis("jacobi", N, (g, d)), N)
+    Af = _exact_float(A)
+    for k in range(N + 1):
+        e = np.zeros(N + 1)
+        e[k] = 1.0
+        assert np.max(np.abs(oracle.cheb2jac(e, float(g), float(d)) - Af[:, k])) < 1e-13 * max(1.0, np.abs(Af).max())
 
 
 @pytest.mark.parametrize("a1,a2", [(F(1, 2), F(-1, 4)), (F(0), F(1, 2)), (F(3, 2), F(0))])
