@@ -227,6 +227,54 @@ def main():
                              f"(sum of degree+1 = {int(np.sum(degs + 1))}), alpha_k ~ N(0,1)(k+1)^-1, "
                              "hipGraph replay, plans reused")
 
+    # ---- config 5: 65536 x degree 255 + 64 x degree 2^18, ultraspherical and Jacobi ----
+    degs5 = np.array([255] * 65536 + [1 << 18] * 64, dtype=np.int64)
+    offs5 = np.concatenate([[0], np.cumsum(degs5 + 1)])
+    g5 = inputs.rng(55)
+    z5 = g5.standard_normal(int(offs5[-1]))
+    kidx = np.arange(int(offs5[-1])) - np.repeat(offs5[:-1], degs5 + 1)
+    flat5 = z5 / (kidx + 1.0)                      # alpha_k ~ N(0,1) (k+1)^-1 per member
+    a5 = torch.from_numpy(flat5).to(dev)
+    b5 = torch.empty_like(a5)
+    conf5 = {}
+    for kname, kind, params in (("ultra_1.5_to_0.5", thx.ULTRA2ULTRA, (1.5, 0.5)),
+                                ("jac2cheb_0.5_-0.25", thx.JAC2CHEB, (0.5, -0.25))):
+        for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
+            bt = thx.Batch(kind, degs5, tolh, prec, params=params)
+            for _ in range(2):
+                bt.execute(a5, b5, graph=True)
+            torch.cuda.synchronize()
+            reps = max(3, args.steps // 5)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bt.execute(a5, b5, graph=True)
+            torch.cuda.synchronize()
+            ms5 = (time.perf_counter() - t0) * 1e3 / reps
+            got = b5.cpu().numpy()
+            worst = 0.0
+            for i in list(range(0, 65536, 8191)) + [65536, 65599]:
+                o, n = int(offs5[i]), int(degs5[i])
+                al, gi = flat5[o:o + n + 1], got[o:o + n + 1]
+                if kind == thx.ULTRA2ULTRA:
+                    r = None if n <= 4096 else inputs.sample_rows(n, 32, seed=i)
+                    ref = oracle.matvec("ultra2ultra", al, params, rows=r)
+                    e = np.max(np.abs((gi if r is None else gi[r]) - ref)) / np.sum(np.abs(al))
+                    e /= max(1.0, 2.0 * n + 1.0)   # entries grow like 2j+1 for 3/2 -> 1/2
+                elif n <= 4096:
+                    e = np.max(np.abs(gi - oracle.jac2cheb(al, *params))) / np.sum(np.abs(al))
+                else:
+                    e = None
+                if e is not None:
+                    worst = max(worst, float(e))
+            conf5[f"{kname}_{pname}"] = {"coeffs_per_s": round(bt.coefficients / (ms5 * 1e-3), 1),
+                                         "ms_per_batch": round(ms5, 4), "buckets": bt.buckets(),
+                                         "max_err_over_l1_sampled": worst}
+            del bt
+    conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
+                         "N(0,1)(k+1)^-1 seed 55, hipGraph replay; ultraspherical errors divided by the "
+                         "entry growth 2N+1; Jacobi checked on the degree-255 members")
+    del a5, b5
+
     copy_gbs = copy_bandwidth(torch)
 
     # ---- CPU oracle on a bounded sample of output rows ----
@@ -277,6 +325,7 @@ def main():
                       "K": K32, "max_err_over_l1": err32, "bar": 5e-6, "hankel_tol": 1e-7,
                       "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim32.items()}},
         "batched": batch_res,
+        "config5": conf5,
         "cheb2leg_fp64": {"coeffs_per_s": round((N + 1) / (msc * 1e-3), 1), "ms_per_step": round(msc, 5),
                           "K": Kc, "max_err_over_l1": errc, "hankel_tol": 1e-17},
     }
