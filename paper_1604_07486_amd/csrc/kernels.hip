@@ -10,9 +10,6 @@
 // plus the O(N^2) direct evaluation used below the FFT crossover (Sec. 4).
 #include "launch.hpp"
 #include "fft_reg.hpp"
-#ifndef THX_PREFETCH_SYM
-#define THX_PREFETCH_SYM 1
-#endif
 #include "thx_device.hpp"
 #include <math.h>
 
@@ -760,28 +757,37 @@ template <typename T, int L2> constexpr int mp_tc() { return mp_tile<T>() / L2 >
 template <typename T, int L2> constexpr int mp_nt() { return nthreads<L2, mp_tc<T, L2>()>(); }
 
 template <typename T>
-MultiPassGeom multipass_geom(int64_t L)
+MultiPassGeom multipass_geom(int64_t L, int64_t row)
 {
     MultiPassGeom g;
     g.L = L;
-    g.L1 = lds_max_len<T>();
+    const bool ok = (row == mp_row_short<T>() || row == mp_row_long<T>()) && L / row >= 2 && L / row <= 1024;
+    if (!ok) row = L / mp_row_short<T>() <= 512 ? mp_row_short<T>() : mp_row_long<T>();
+    g.L1 = row;
     g.L2 = L / g.L1;
     const int64_t tc = mp_tile<T>() / g.L2;
     g.TC = tc > 64 ? 64 : tc;
     return g;
 }
-template MultiPassGeom multipass_geom<double>(int64_t);
-template MultiPassGeom multipass_geom<float>(int64_t);
+template MultiPassGeom multipass_geom<double>(int64_t, int64_t);
+template MultiPassGeom multipass_geom<float>(int64_t, int64_t);
 
-template <typename T, int L2>
+// w_L^e for 0 <= e < L = L1 L2, from twA[e] = w_L^e (e < L1) and twL2[i] = w_L^{i L1}
+template <typename T, int L1>
+__device__ __forceinline__ cpx<T> tw_L(const cpx<T> *__restrict__ twA, const cpx<T> *__restrict__ twL2, int e)
+{
+    return cmul(twA[e & (L1 - 1)], twL2[e >> ilog2(L1)]);
+}
+
+template <typename T, int L1, int L2>
 __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
     int nslots, const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
     const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA)
 {
     constexpr int TC = mp_tc<T, L2>();
-    using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
-    constexpr int L1 = (int)lds_max_len<T>();
+    constexpr int NT = mp_nt<T, L2>();
+    using F = RegFFT<T, L2, TC, NT, RMAX>;
     constexpr int64_t L = (int64_t)L1 * L2;
     __shared__ cpx<T> lds[F::LDS];
     constexpr int tiles = L1 / TC;
@@ -802,31 +808,48 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     }
     F::forward(v, lds, twL2);
     cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
+    // Twiddle w_L^{a1 k2}.  The thread's column a1 is the same in all its
+    // butterfly groups p and its rows are k2 = j_p + q L2/RL, so the factor is
+    // w_L^{a1 j_p} (one table pair per group) times the q-th power of
+    // w_L^{a1 L2/RL} (powers of two from the tables, the rest as products).
+    constexpr int RL = F::R_LAST, PG = F::E / RL;
+    static_assert(NT % TC == 0, "column of a thread fixed across groups");
+    const int a1 = a1_0 + (int)threadIdx.x % TC;
+    cpx<T> st[RL];
+    st[0] = cpx<T>{1, 0};
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) {
-        int k2, c;
-        F::out_pos(e, k2, c);
-        const int a1 = a1_0 + c;
-        const int64_t ex = (int64_t)a1 * k2; // < L
-        const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
-        st_stream(Ub + a1 + (int64_t)L1 * k2, cmul(v[e], t));
+    for (int q = 1; q < RL; ++q) {
+        if ((q & (q - 1)) == 0) st[q] = tw_L<T, L1>(twA, twL2, a1 * q * (L2 / RL));
+        else st[q] = cmul(st[q & (q - 1)], st[q & -q]);
+    }
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+        const int j = ((int)threadIdx.x + NT * p) / TC;
+        const cpx<T> bp = tw_L<T, L1>(twA, twL2, a1 * j);
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+            const int k2 = j + q * (L2 / RL);
+            const cpx<T> t = q == 0 ? bp : cmul(bp, st[q]);
+            st_stream(Ub + a1 + (int64_t)L1 * k2, cmul(v[p * RL + q], t));
+        }
     }
 }
 
 // the row pass keeps radix 16: two LDS exchanges per transform instead of three
 constexpr int RMAX_ROW = 16;
-template <typename T>
-constexpr int p2_threads() { return fft_threads((int)lds_max_len<T>(), 1, RMAX_ROW); }
+template <typename T, int L1>
+constexpr int p2_threads() { return fft_threads(L1, 1, RMAX_ROW); }
 
-template <typename T>
-__global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, int nsb, const cpx<T> *__restrict__ that_perm,
-                                               const cpx<T> *__restrict__ twL1,
-                                               const cpx<T> *__restrict__ twA,
-                                               const cpx<T> *__restrict__ twL2, int full,
-                                               cpx<T> *__restrict__ out, T scale)
+template <typename T, int L1>
+__global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int L2, int nsb,
+                                                                const cpx<T> *__restrict__ that_perm,
+                                                                const cpx<T> *__restrict__ twL1,
+                                                                const cpx<T> *__restrict__ twA,
+                                                                const cpx<T> *__restrict__ twL2, int full,
+                                                                cpx<T> *__restrict__ out, T scale)
 {
-    constexpr int L1 = (int)lds_max_len<T>();
-    using F = RegFFT<T, L1, 1, p2_threads<T>(), RMAX_ROW>;
+    constexpr int NT = p2_threads<T, L1>();
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW>;
     __shared__ cpx<T> lds[F::LDS];
     int k2, sb;
     xcd_map(blockIdx.x, L2, nsb, k2, sb);
@@ -839,19 +862,6 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         F::in_pos(e, pos, c);
         v[e] = ld_stream(row + pos);
     }
-#if THX_PREFETCH_SYM
-    // symbol row read now so that its latency overlaps the forward transform
-    cpx<T> sym[F::E];
-    if (full) {
-        const cpx<T> *tp0 = that_perm + (int64_t)k2 * L1;
-#pragma unroll
-        for (int e = 0; e < F::E; ++e) {
-            int k1, c;
-            F::out_pos(e, k1, c);
-            sym[e] = tp0[k1];
-        }
-    }
-#endif
     F::forward(v, lds, twL1);
     if (!full) {
 #pragma unroll
@@ -862,10 +872,6 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         }
         return;
     }
-#if THX_PREFETCH_SYM
-#pragma unroll
-    for (int e = 0; e < F::E; ++e) v[e] = cmul(v[e], sym[e]);
-#else
     const cpx<T> *tp = that_perm + (int64_t)k2 * L1;
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -873,27 +879,34 @@ __global__ __launch_bounds__((p2_threads<T>())) void k_mp_p2(cpx<T> *U, int L2, 
         F::out_pos(e, k1, c);
         v[e] = cmul(v[e], tp[k1]);
     }
-#endif
     F::inverse(v, lds, twL1);
+    // Conjugate twiddle w_L^{-a1 k2} with a1 = j_p + r L1/RF (j_p = threadIdx.x
+    // + NT p): a per-thread factor w_L^{j_p k2} times the workgroup-uniform
+    // w_L^{r k2 L1/RF}, so only one table pair per group is gathered.
+    constexpr int RF = F::R_FIRST, PG = F::E / RF;
+    cpx<T> bp[PG];
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) {
-        int a1, c;
-        F::in_pos(e, a1, c);
-        const int64_t ex = (int64_t)a1 * k2;
-        const cpx<T> t = cmul(twA[ex % L1], twL2[ex / L1]);
-        st_stream(row + a1, cmulc(v[e], t));
+    for (int p = 0; p < PG; ++p) bp[p] = tw_L<T, L1>(twA, twL2, ((int)threadIdx.x + NT * p) * k2);
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const cpx<T> sr = tw_L<T, L1>(twA, twL2, r * (L1 / RF) * k2);
+#pragma unroll
+        for (int p = 0; p < PG; ++p) {
+            const int a1 = (int)threadIdx.x + NT * p + r * (L1 / RF);
+            const cpx<T> t = r == 0 ? bp[p] : cmul(bp[p], sr);
+            st_stream(row + a1, cmulc(v[p * RF + r], t));
+        }
     }
 }
 
-template <typename T, int L2>
-__global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
+template <typename T, int L1, int L2>
+__global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_eu(4))) void k_mp_p3(
     const cpx<T> *__restrict__ U, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
     int nslots, int spg, cpx<T> *__restrict__ W, int gofs, int64_t batch,
     const cpx<T> *__restrict__ twL2)
 {
     constexpr int TC = mp_tc<T, L2>();
     using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
-    constexpr int L1 = (int)lds_max_len<T>();
     constexpr int64_t L = (int64_t)L1 * L2;
     constexpr int E = F::E;
     __shared__ cpx<T> lds[F::LDS];
@@ -932,64 +945,109 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p3(
     }
 }
 
+// Column lengths instantiated for each row length (L1 L2 <= MP_LMAX).
 #define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename T, int L1>
+bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
+              int nslots, const void *src, void *U, int64_t batch, const void *twL2, const void *twA,
+              hipStream_t s)
+{
+    switch (g.L2) {
+#define THX_P1(LL2)                                                                                       \
+    case LL2:                                                                                             \
+        if constexpr ((int64_t)L1 * LL2 <= MP_LMAX) {                                                     \
+            k_mp_p1<T, L1, LL2><<<dim3((unsigned)(L1 / mp_tc<T, LL2>() * nslots * batch)),               \
+                                  mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell, \
+                                                           slot0, nslots, (const cpx<T> *)src,            \
+                                                           (cpx<T> *)U, batch, (const cpx<T> *)twL2,      \
+                                                           (const cpx<T> *)twA);                          \
+            return true;                                                                                  \
+        } else {                                                                                          \
+            return false;                                                                                 \
+        }
+        THX_L2_CASES(THX_P1)
+#undef THX_P1
+    default: return false;
+    }
+}
 
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
                   int slot0, int nslots, const void *src, void *U, int64_t batch, const void *twL2,
                   const void *twA, hipStream_t s)
 {
-    switch (g.L2) {
-#define THX_P1(LL2)                                                                                   \
-    case LL2:                                                                                         \
-        if (LL2 * (int64_t)lds_max_len<T>() > (int64_t)1 << 22) return false;                         \
-        k_mp_p1<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>() * nslots * batch)),                 \
-                          mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,     \
-                                                   slot0, nslots, (const cpx<T> *)src, (cpx<T> *)U,   \
-                                                   batch, (const cpx<T> *)twL2, (const cpx<T> *)twA); \
-        return true;
-        THX_L2_CASES(THX_P1)
-#undef THX_P1
-    default: return false;
-    }
+    if (g.L1 == mp_row_short<T>())
+        return mp_p1_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, src, U, batch, twL2, twA, s);
+    if (g.L1 == mp_row_long<T>())
+        return mp_p1_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, src, U, batch, twL2, twA, s);
+    return false;
 }
 template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
 template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+
+template <typename T, int L1>
+void mp_p2_run(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,
+               const void *twL1, const void *twA, const void *twL2, bool full, void *out, double scale,
+               hipStream_t s)
+{
+    dim3 grid((unsigned)(g.L2 * nslots * batch));
+    k_mp_p2<T, L1><<<grid, p2_threads<T, L1>(), 0, s>>>(
+        (cpx<T> *)U, (int)g.L2, (int)(nslots * batch), (const cpx<T> *)that_perm, (const cpx<T> *)twL1,
+        (const cpx<T> *)twA, (const cpx<T> *)twL2, full ? 1 : 0, (cpx<T> *)out, (T)scale);
+}
 
 template <typename T>
 bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,
                   const void *twL1, const void *twA, const void *twL2, bool full, void *out,
                   double scale, hipStream_t s)
 {
-    if (g.L1 != lds_max_len<T>() || g.L2 < 2 || g.L2 > 1024) return false;
-    dim3 grid((unsigned)(g.L2 * nslots * batch));
-    k_mp_p2<T><<<grid, p2_threads<T>(), 0, s>>>((cpx<T> *)U, (int)g.L2, (int)(nslots * batch),
-                                                (const cpx<T> *)that_perm,
-                                    (const cpx<T> *)twL1, (const cpx<T> *)twA,
-                                    (const cpx<T> *)twL2, full ? 1 : 0, (cpx<T> *)out, (T)scale);
+    if (g.L2 < 2 || g.L2 > 1024 || g.L1 * g.L2 > MP_LMAX) return false;
+    if (g.L1 == mp_row_short<T>())
+        mp_p2_run<T, (int)mp_row_short<T>()>(g, U, nslots, batch, that_perm, twL1, twA, twL2, full, out, scale, s);
+    else if (g.L1 == mp_row_long<T>())
+        mp_p2_run<T, (int)mp_row_long<T>()>(g, U, nslots, batch, that_perm, twL1, twA, twL2, full, out, scale, s);
+    else
+        return false;
     return true;
 }
 template bool launch_mp_p2<double>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
 template bool launch_mp_p2<float>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
+
+template <typename T, int L1>
+bool mp_p3_l2(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell, int slot0,
+              int nslots, int spg, int G, void *Wpart, int gofs, int64_t batch, const void *twL2,
+              hipStream_t s)
+{
+    switch (g.L2) {
+#define THX_P3(LL2)                                                                                   \
+    case LL2:                                                                                         \
+        if constexpr ((int64_t)L1 * LL2 <= MP_LMAX) {                                                 \
+            k_mp_p3<T, L1, LL2><<<dim3((unsigned)(L1 / mp_tc<T, LL2>()), (unsigned)G, (unsigned)batch), \
+                                  mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)U, nc, n,                  \
+                                                           (const cpx<T> *)ell, slot0, nslots, spg,   \
+                                                           (cpx<T> *)Wpart, gofs, batch,              \
+                                                           (const cpx<T> *)twL2);                     \
+            return true;                                                                              \
+        } else {                                                                                      \
+            return false;                                                                             \
+        }
+        THX_L2_CASES(THX_P3)
+#undef THX_P3
+    default: return false;
+    }
+}
 
 template <typename T>
 bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell,
                   int slot0, int nslots, int spg, int G, void *Wpart, int gofs, int64_t batch,
                   const void *twL2, hipStream_t s)
 {
-    switch (g.L2) {
-#define THX_P3(LL2)                                                                                   \
-    case LL2:                                                                                         \
-        if (LL2 * (int64_t)lds_max_len<T>() > (int64_t)1 << 22) return false;                         \
-        k_mp_p3<T, LL2><<<dim3((unsigned)(g.L1 / mp_tc<T, LL2>()), (unsigned)G, (unsigned)batch),     \
-                          mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)U, nc, n, (const cpx<T> *)ell,     \
-                                                   slot0, nslots, spg, (cpx<T> *)Wpart, gofs, batch,  \
-                                                   (const cpx<T> *)twL2);                             \
-        return true;
-        THX_L2_CASES(THX_P3)
-#undef THX_P3
-    default: return false;
-    }
+    if (g.L1 == mp_row_short<T>())
+        return mp_p3_l2<T, (int)mp_row_short<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch, twL2, s);
+    if (g.L1 == mp_row_long<T>())
+        return mp_p3_l2<T, (int)mp_row_long<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch, twL2, s);
+    return false;
 }
 template bool launch_mp_p3<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, int, void *, int, int64_t, const void *, hipStream_t);
 template bool launch_mp_p3<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, int, void *, int, int64_t, const void *, hipStream_t);

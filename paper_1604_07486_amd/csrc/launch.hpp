@@ -115,9 +115,16 @@ void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, co
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 
 // ---- a5: Toeplitz products ---------------------------------------------------------
-// Largest length handled by one workgroup in LDS, and the row length of the
-// three-pass scheme (same value).
+// Largest length handled by one workgroup in LDS.
 template <typename T> constexpr int64_t lds_max_len() { return sizeof(T) == 8 ? 4096 : 8192; }
+// Row lengths of the three-pass scheme.  The short row takes half the LDS of
+// the long one, so twice as many row workgroups share a CU and the loads,
+// transforms and stores of different rows overlap; it is the default while
+// the columns stay at most 512 long, where a column tile still spans full
+// 128-byte segments.  Longest transform: MP_LMAX.
+template <typename T> constexpr int64_t mp_row_short() { return sizeof(T) == 8 ? 2048 : 4096; }
+template <typename T> constexpr int64_t mp_row_long() { return sizeof(T) == 8 ? 4096 : 8192; }
+constexpr int64_t MP_LMAX = (int64_t)1 << 22;
 
 // single-workgroup path: W[g] = sum_{s in group g} ell_s o IFFT(FFT(ell_s o X) . that)
 template <typename T>
@@ -132,7 +139,9 @@ bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double
 struct MultiPassGeom {
     int64_t L, L1, L2, TC;
 };
-template <typename T> MultiPassGeom multipass_geom(int64_t L);
+// geometry for length L; `row` selects mp_row_short / mp_row_long, any other
+// value (or one that leaves the columns outside 2..1024) the default
+template <typename T> MultiPassGeom multipass_geom(int64_t L, int64_t row = 0);
 // P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr)
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,

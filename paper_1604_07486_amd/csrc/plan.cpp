@@ -433,7 +433,10 @@ void build_fft(thx_plan *p, hipStream_t s)
         }
     } else {
         p->path = 2;
-        p->geom = f64 ? multipass_geom<double>(L) : multipass_geom<float>(L);
+        // THX_ROW_LEN: row length of the three-pass scheme (tuning experiments)
+        int64_t row = 0;
+        if (const char *e = getenv("THX_ROW_LEN")) row = atoll(e);
+        p->geom = f64 ? multipass_geom<double>(L, row) : multipass_geom<float>(L, row);
         const MultiPassGeom &g = p->geom;
         p->twL1 = make_twiddles(p, g.L1, g.L1, s, 0);
         p->twL2 = make_twiddles(p, g.L2, g.L2, s, 1);

@@ -147,6 +147,17 @@ def test_leg2cheb_fft_fp32(thx, N):
     _check_full(thx, thx.LEG2CHEB, N, thx.FP32_BULK, flags=thx.FLAG_FORCE_FFT, seed=N)
 
 
+# both row lengths of the three-pass scheme (THX_ROW_LEN is read at plan
+# creation; 0 = the default choice), several column lengths each
+@pytest.mark.parametrize("N,prec,row", [(20000, 0, 2048), (20000, 0, 4096), (40000, 1, 4096), (40000, 1, 8192),
+                                        (150000, 0, 2048), (150000, 0, 4096), (150000, 1, 4096),
+                                        (150000, 1, 8192)])
+def test_leg2cheb_row_lengths(thx, N, prec, row, monkeypatch):
+    monkeypatch.setenv("THX_ROW_LEN", str(row))
+    plan, _ = _check_full(thx, thx.LEG2CHEB, N, prec, flags=thx.FLAG_FORCE_FFT, seed=N + row)
+    assert plan.path == 2
+
+
 @pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 512])
 def test_leg2cheb_direct(thx, N):
     _check_full(thx, thx.LEG2CHEB, N, thx.FP64, flags=thx.FLAG_FORCE_DIRECT, seed=N)
