@@ -60,6 +60,8 @@ typedef enum {
 /* plan flags */
 #define THX_FLAG_FORCE_DIRECT 1u /* always use the O(N^2) direct evaluation         */
 #define THX_FLAG_FORCE_FFT 2u    /* never use the direct evaluation (testing)        */
+#define THX_FLAG_NO_DENSE 4u     /* direct evaluation entry by entry instead of the
+                                    materialised dense matrix (testing, plan memory) */
 
 typedef struct thx_plan thx_plan;
 
@@ -88,8 +90,9 @@ thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, 
 /* beta[b][0..N] = A alpha[b][0..N] for b < batch (Fig. 1 steps 3-5), N = degree
  * with 0 <= degree <= the plan's degree.  alpha, beta: device doubles, row stride
  * ld >= degree+1; entries beyond N in each row are neither read nor written.
+ * batch <= 65535 except on the dense path (thx_plan_path 3), which has no limit.
  * Errors: THX_INVALID_ARGUMENT (null plan, null pointers with batch > 0,
- * degree out of range, ld too small, batch < 0), THX_HIP_ERROR. */
+ * degree out of range, ld too small, batch < 0 or above the limit), THX_HIP_ERROR. */
 thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
                        int64_t batch, int64_t ld, hipStream_t stream);
 
@@ -101,7 +104,11 @@ thx_status thx_plan_destroy(thx_plan *plan);
  * rank: number of FFT slots K (for parity-split kinds max(K_even, K_odd)).
  * rank_part: rank of Hankel part `part` (0 = even / only, 1 = odd), -1 if absent.
  * fft_length: circulant-embedding length L (0 on the direct path).
- * path: 0 direct, 1 single-workgroup LDS FFT, 2 three-pass FFT. */
+ * path: 0 direct (entries generated per output row), 1 single-workgroup LDS
+ * FFT, 2 three-pass FFT, 3 dense: below the FFT crossover (degree + 1 <= 512,
+ * THX_FLAG_NO_DENSE not set) the plan materialises the (degree+1)^2 matrix once
+ * by the direct evaluation of the unit vectors, and every execution is one
+ * double-precision matrix-core product with it (both precisions). */
 int32_t thx_plan_rank(const thx_plan *plan);
 int32_t thx_plan_rank_part(const thx_plan *plan, int part);
 int64_t thx_plan_fft_length(const thx_plan *plan);
@@ -141,8 +148,11 @@ thx_status thx_cache_clear(void);
  * grouped by FFT length; each group gets one plan at its largest degree (the
  * Hankel part for degree N is the leading block of the one for a larger
  * degree, so the factorisation holds for every member).  Degrees up to the
- * direct crossover (THX_DIRECT_MAX, default 512, or flags) use the O(N^2)
- * kernel.  All workspace is allocated here; thx_batch_create synchronises
+ * direct crossover (THX_DIRECT_MAX, default 512, or flags) form one bucket
+ * evaluated directly: by the dense matrix product (path 3) when the largest of
+ * them is below 512 and THX_FLAG_NO_DENSE is not set, else entry by entry
+ * (buckets of at most 65535 members).  All workspace is allocated here;
+ * thx_batch_create synchronises
  * `stream`.  Errors as thx_plan_create, plus THX_INVALID_ARGUMENT for a
  * negative degree or count. */
 typedef struct thx_batch thx_batch;
@@ -189,7 +199,8 @@ enum {
     THX_PHASE_ROW0 = 5,     /* cheb2leg row 0 by a direct dot product               */
     THX_PHASE_UNPACK = 6,   /* beta = D1 w (Fig. 1 step 5)                          */
     THX_PHASE_DIRECT = 7,   /* O(N^2) direct evaluation                             */
-    THX_NPHASES = 8
+    THX_PHASE_DENSE = 8,    /* product with the materialised matrix (path 3)        */
+    THX_NPHASES = 9
 };
 thx_status thx_plan_enable_timing(thx_plan *plan, int enable);
 thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);

@@ -586,6 +586,111 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s)
     k_zero<<<(unsigned)((count + 255) / 256), 256, 0, s>>>((double *)p, count);
 }
 
+__global__ void k_identity(double *I, int64_t n, int64_t ld)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) I[k * ld + k] = 1.0;
+}
+void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s)
+{
+    if (n <= 0) return;
+    k_identity<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(I, n, ld);
+}
+
+// ============================================================================
+// Dense path (short vectors): beta_b = A alpha_b as one batched product
+// ============================================================================
+// The matrix is an O(N^2) object anyway below the FFT crossover; materialised
+// once per plan, every execution is a contraction over k on the matrix cores:
+//   C[b][j] = sum_k alpha[b][k] At[k][j],   At[k][j] = A[j][k] = 0 for k < j.
+// Workgroup: 64 vectors x one chunk of up to 256 outputs; wave w owns the
+// 16-column output tiles w, w+4, w+8, w+12 (interleaved so that the triangular
+// work is balanced).  The alpha tile goes through LDS in chunks of 32 k; the
+// matrix operand is read straight from global memory (small, cache-resident).
+// v_mfma_f64_16x16x4f64 lane layout: operand a = X[m = lane&15][k = lane>>4],
+// operand b = Y[k = lane>>4][n = lane&15], result element i of a lane is
+// D[(lane>>4) + 4i][lane&15].
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int DN_BM = 64, DN_BN = 256, DN_BK = 32, DN_LDW = DN_BK + 1, DN_NT = 256;
+static_assert(DENSE_PAD % DN_BK == 0 && DN_BN % DN_BK == 0, "dense tiling");
+
+__global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
+                                                 const double *__restrict__ alpha, int64_t ld,
+                                                 double *__restrict__ beta, int64_t N0, int64_t batch)
+{
+    __shared__ double xs[DN_BM * DN_LDW];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b0 = (int64_t)blockIdx.x * DN_BM;
+    const int j0 = blockIdx.y * DN_BN;
+    const int jend = min(npad, j0 + DN_BN);
+    // loader: column c of the chunk, rows r0 + 8e
+    constexpr int LR = DN_BM * DN_BK / DN_NT; // 8 rows per thread
+    const int c = threadIdx.x % DN_BK, r0 = threadIdx.x / DN_BK;
+    int64_t lbase[LR], ln[LR];
+#pragma unroll
+    for (int e = 0; e < LR; ++e) {
+        const int64_t b = b0 + r0 + 8 * e;
+        if (b < batch) vec_of(vr, b, ld, N0, lbase[e], ln[e]);
+        else lbase[e] = 0, ln[e] = -1;
+    }
+    v4d acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[mt][u] = v4d{0, 0, 0, 0};
+    // At[k][j] = 0 for k < j, so the chunk starting at output j0 needs k >= j0 only
+    for (int kc = j0; kc < npad; kc += DN_BK) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < LR; ++e) {
+            const int64_t k = kc + c;
+            xs[(r0 + 8 * e) * DN_LDW + c] = k <= ln[e] ? alpha[lbase[e] + k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < DN_BK; ks += 4) {
+            const int k0 = kc + ks;
+            double a[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) a[mt] = xs[(16 * mt + (lane & 15)) * DN_LDW + ks + (lane >> 4)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jt = j0 + 16 * (w + 4 * u);
+                if (jt >= jend || k0 + 4 <= jt) continue; // outside the matrix, or all of At zero there
+                const double bv = At[(int64_t)(k0 + (lane >> 4)) * npad + jt + (lane & 15)];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt], bv, acc[mt][u], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int jt = j0 + 16 * (w + 4 * u);
+        if (jt >= jend) continue;
+        const int64_t j = jt + (lane & 15);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t b = b0 + 16 * mt + (lane >> 4) + 4 * i;
+                if (b >= batch) continue;
+                int64_t base, n;
+                vec_of(vr, b, ld, N0, base, n);
+                if (j <= n) beta[base + j] = acc[mt][u][i];
+            }
+    }
+}
+
+void launch_dense(const double *At, int64_t npad, const int64_t *off, const int64_t *deg,
+                  const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
+                  hipStream_t s)
+{
+    if (batch <= 0) return;
+    dim3 grid((unsigned)((batch + DN_BM - 1) / DN_BM), (unsigned)((npad + DN_BN - 1) / DN_BN));
+    k_dense<<<grid, DN_NT, 0, s>>>(At, (int)npad, VecRef{off, deg}, alpha, ld, beta, N, batch);
+}
+
 // ============================================================================
 // a5: sums of diagonally scaled Toeplitz products, eq. (Cdecomposition)
 // ============================================================================

@@ -113,6 +113,17 @@ void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, co
                    int64_t ld, double *beta, int64_t N, int64_t batch, const double *tsym,
                    const double *hk, hipStream_t s);
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
+// I[k][k] = 1 for k < n (row stride ld; the rest must already be zero)
+void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s);
+
+// ---- dense path: beta_b = A alpha_b with A materialised ----------------------------
+// At[k][j] = A[j][k], row-major with stride npad (a multiple of DENSE_PAD), zero
+// outside 0..N and for k < j (A upper triangular).  off / deg as for pack.
+constexpr int64_t DENSE_PAD = 32;
+constexpr int64_t DENSE_MAX = 512; // largest degree + 1 with a materialised matrix
+void launch_dense(const double *At, int64_t npad, const int64_t *off, const int64_t *deg,
+                  const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
+                  hipStream_t s);
 
 // ---- a5: Toeplitz products ---------------------------------------------------------
 // Largest length handled by one workgroup in LDS.

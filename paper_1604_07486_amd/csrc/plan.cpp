@@ -133,7 +133,9 @@ struct thx_plan {
     thx_precision prec = THX_FP64;
     uint32_t flags = 0;
     KindDesc kd{};
-    int path = 0;   // 0 direct, 1 LDS, 2 three-pass
+    int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense
+    double *dense = nullptr; // path 3: At[k][j] = A[j][k], stride dense_ld
+    int64_t dense_ld = 0;
     int64_t nc = 0; // complex lanes
     int parts = 0;
     int64_t npart[2] = {0, 0}, a0[2] = {0, 0};
@@ -201,6 +203,7 @@ struct thx_plan {
         delete[] pivots[1];
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         dfree(tmp);
+        dfree(dense);
         delete next;
     }
 };
@@ -542,6 +545,49 @@ thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_
     return r;
 }
 
+void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems);
+
+// Materialise the matrix of a plan whose stages all run the direct evaluation:
+// row k of the identity goes through them and comes out as column k of A, so
+// reflections, normalisations, special rows and two-stage products need no
+// formulas of their own here.
+bool dense_eligible(const thx_plan *p, uint32_t flags)
+{
+    if (flags & (THX_FLAG_FORCE_FFT | THX_FLAG_NO_DENSE)) return false;
+    if (p->N + 1 > DENSE_MAX) return false;
+    for (const thx_plan *q = p; q; q = q->next)
+        if (q->path != 0) return false;
+    return true;
+}
+
+void build_dense(thx_plan *p, hipStream_t s)
+{
+    const int64_t n1 = p->N + 1;
+    const int64_t npad = (n1 + DENSE_PAD - 1) / DENSE_PAD * DENSE_PAD;
+    double *At = dalloc<double>(npad * npad);
+    double *I = nullptr;
+    try {
+        I = dalloc<double>(n1 * npad);
+        launch_zero(At, npad * npad * (int64_t)sizeof(double), s);
+        launch_zero(I, n1 * npad * (int64_t)sizeof(double), s);
+        launch_identity(I, n1, npad, s);
+        execute_core(p, nullptr, nullptr, I, At, p->N, n1, npad, s, n1 * npad);
+        hip_check(hipStreamSynchronize(s));
+    } catch (...) {
+        dfree(I);
+        dfree(At);
+        throw;
+    }
+    dfree(I);
+    dfree(p->tmp); // the stages' intermediate is not used by the dense product
+    p->tmp = nullptr;
+    p->tmp_elems = 0;
+    p->dense = At;
+    p->dense_ld = npad;
+    p->path = 3;
+}
+
 thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
                        double tol, thx_precision prec, uint32_t flags, hipStream_t s)
 {
@@ -552,9 +598,23 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
     double pv[4] = {0, 0, 0, 0};
     thx_status vs = validate_kind(kind, params, nparams, pv);
     if (vs != THX_OK) return vs;
-    if (kind == THX_JAC2JAC || kind == THX_JAC2CHEB || kind == THX_CHEB2JAC)
-        return create_jacobi(out, kind, pv, degree, tol, prec, flags, s);
-    return create_single(out, kind, pv, nullptr, degree, tol, prec, flags, s);
+    thx_status r = (kind == THX_JAC2JAC || kind == THX_JAC2CHEB || kind == THX_CHEB2JAC)
+                       ? create_jacobi(out, kind, pv, degree, tol, prec, flags, s)
+                       : create_single(out, kind, pv, nullptr, degree, tol, prec, flags, s);
+    if ((r != THX_OK && r != THX_TOL_NOT_REACHED) || !dense_eligible(*out, flags)) return r;
+    try {
+        build_dense(*out, s);
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        delete *out;
+        *out = nullptr;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        delete *out;
+        *out = nullptr;
+        return THX_OUT_OF_MEMORY;
+    }
+    return r;
 }
 
 thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const JacStage *jac, int64_t degree,
@@ -755,6 +815,12 @@ void ensure_tmp(thx_plan *p, int64_t elems)
 void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems)
 {
+    if (p->dense) {
+        PhaseTimer t(p, THX_PHASE_DENSE, s);
+        launch_dense(p->dense, p->dense_ld, off, deg, alpha, ld, beta, degree, batch, s);
+        launch_check();
+        return;
+    }
     if (!p->next) {
         execute_stage(p, off, deg, alpha, beta, degree, batch, ld, s);
         return;
@@ -785,7 +851,7 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     if (!p || degree < 0 || degree > p->N || batch < 0 || ld < degree + 1) return THX_INVALID_ARGUMENT;
     if (batch == 0) return THX_OK;
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
-    if (batch > 65535) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
+    if (batch > 65535 && !p->dense) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
     try {
         execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s, batch * ld);
     } catch (const HipFail &f) {
@@ -894,8 +960,13 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
     try {
         for (auto &kv : groups) {
             const std::vector<int64_t> &idx = kv.second;
-            for (size_t c0 = 0; c0 < idx.size(); c0 += MAX_BUCKET_MEMBERS) {
-                const size_t c1 = std::min(idx.size(), c0 + (size_t)MAX_BUCKET_MEMBERS);
+            // the dense product has no per-vector grid limit: one bucket
+            int64_t gmax = 0;
+            for (int64_t i : idx) gmax = std::max(gmax, degrees[i]);
+            const bool dense = kv.first == 0 && !(flags & THX_FLAG_NO_DENSE) && gmax + 1 <= DENSE_MAX;
+            const size_t chunk = dense ? idx.size() : (size_t)MAX_BUCKET_MEMBERS;
+            for (size_t c0 = 0; c0 < idx.size(); c0 += chunk) {
+                const size_t c1 = std::min(idx.size(), c0 + chunk);
                 thx_batch::Bucket bk;
                 std::vector<int64_t> ho, hd;
                 for (size_t m = c0; m < c1; ++m) {
@@ -904,21 +975,29 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                     bk.Nmax = std::max(bk.Nmax, degrees[idx[m]]);
                 }
                 bk.members = (int64_t)ho.size();
-                const uint32_t f = kv.first == 0 ? THX_FLAG_FORCE_DIRECT : THX_FLAG_FORCE_FFT;
+                const uint32_t f = (kv.first == 0 ? THX_FLAG_FORCE_DIRECT : THX_FLAG_FORCE_FFT) |
+                                   (flags & THX_FLAG_NO_DENSE);
                 thx_status st = create_plan(&bk.plan, kind, params, nparams, bk.Nmax, tol, prec, f, s);
                 if (st == THX_TOL_NOT_REACHED) result = st;
                 else if (st != THX_OK) {
                     delete b;
                     return st;
                 }
-                bk.L = bk.plan->path == 0 ? 0 : bk.plan->L;
+                if (!bk.plan->dense && bk.members > MAX_BUCKET_MEMBERS) {
+                    delete bk.plan;
+                    delete b;
+                    return THX_UNSUPPORTED;
+                }
+                bk.L = (bk.plan->path == 0 || bk.plan->path == 3) ? 0 : bk.plan->L;
                 bk.d_off = dalloc<int64_t>(bk.members);
                 bk.d_deg = dalloc<int64_t>(bk.members);
                 hip_check(hipMemcpyAsync(bk.d_off, ho.data(), sizeof(int64_t) * ho.size(), hipMemcpyHostToDevice, s));
                 hip_check(hipMemcpyAsync(bk.d_deg, hd.data(), sizeof(int64_t) * hd.size(), hipMemcpyHostToDevice, s));
-                for (thx_plan *q = bk.plan; q; q = q->next)
-                    if (q->path != 0) ensure_workspace(q, bk.members);
-                if (bk.plan->next) ensure_tmp(bk.plan, acc);
+                if (!bk.plan->dense) {
+                    for (thx_plan *q = bk.plan; q; q = q->next)
+                        if (q->path != 0) ensure_workspace(q, bk.members);
+                    if (bk.plan->next) ensure_tmp(bk.plan, acc);
+                }
                 b->buckets.push_back(bk);
                 hip_check(hipStreamSynchronize(s));
             }
@@ -1026,13 +1105,13 @@ int64_t thx_plan_fft_length(const thx_plan *p)
 {
     if (!p) return -1;
     int64_t L = 0;
-    for (const thx_plan *q = p; q; q = q->next) L = std::max<int64_t>(L, q->path == 0 ? 0 : q->L);
+    for (const thx_plan *q = p; q; q = q->next) L = std::max<int64_t>(L, (q->path == 1 || q->path == 2) ? q->L : 0);
     return L;
 }
 int32_t thx_plan_path(const thx_plan *p) { return p ? p->path : -1; }
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {
-    if (!p || part < 0 || part >= p->parts || p->path == 0) return -1.0;
+    if (!p || part < 0 || part >= p->parts || p->path == 0 || p->path == 3) return -1.0;
     return p->dfinal[part];
 }
 

@@ -158,9 +158,12 @@ def test_leg2cheb_row_lengths(thx, N, prec, row, monkeypatch):
     assert plan.path == 2
 
 
-@pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 512])
-def test_leg2cheb_direct(thx, N):
-    _check_full(thx, thx.LEG2CHEB, N, thx.FP64, flags=thx.FLAG_FORCE_DIRECT, seed=N)
+@pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 511, 512])
+@pytest.mark.parametrize("dense", [True, False])
+def test_leg2cheb_direct(thx, N, dense):
+    flags = thx.FLAG_FORCE_DIRECT | (0 if dense else thx.FLAG_NO_DENSE)
+    plan, _ = _check_full(thx, thx.LEG2CHEB, N, thx.FP64, flags=flags, seed=N)
+    assert plan.path == (3 if dense and N + 1 <= 512 else 0)
 
 
 @pytest.mark.parametrize("p", [0.0, 0.5, 2.0])
@@ -337,6 +340,74 @@ def test_batch_empty_and_bad_degree(thx):
 
 
 # ---------------------------------------------------------------------------
+# Dense path (path 3): the matrix is materialised once per plan from the
+# direct evaluation of the unit vectors; each execution is one matrix-core
+# product.  It computes in double precision for both precisions, so both are
+# held to the double-precision bar.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,params,N", [
+    (0, (), 255), (0, (), 100), (0, (), 33),
+    (1, (), 300),                 # cheb2leg: row 0 by the direct dot product
+    (2, (1.5, 0.5), 255),         # ultraspherical, integer step (banded entries)
+    (2, (0.75, 0.25), 200),
+    (4, (0.5, -0.25), 150),       # Laguerre
+])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_matches_oracle(thx, kind, params, N, prec):
+    plan, _ = _check_full(thx, kind, N, prec, params, flags=0, seed=N + kind, bar=TOL64,
+                          scale_bar=(kind == 2))
+    assert plan.path == 3 and plan.fft_length == 0
+
+
+def test_dense_large_batch_subdegree_ld(thx):
+    import torch
+    N, batch, ld = 100, 70000, 105                     # more vectors than one grid dimension holds
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64)
+    assert plan.path == 3
+    alpha = inputs.coeffs(ld - 1, 1.0, seed=21, batch=batch)
+    a = _dev(alpha)
+    rng = inputs.rng(22)
+    pick = np.concatenate([[0, 1, batch - 1], rng.integers(0, batch, 61)])
+    for deg in (N, 60):
+        print(f"[case] dense batch={batch} ld={ld} degree={deg}", flush=True)
+        b = torch.full_like(a, 7.0)
+        plan.execute(a, b, degree=deg)
+        b2 = torch.empty_like(a).copy_(b)
+        plan.execute(a, b2, degree=deg)
+        torch.cuda.synchronize()
+        assert torch.equal(b, b2)                      # deterministic
+        got = b.cpu().numpy()
+        for i in pick:
+            ref = oracle.matvec("leg2cheb", alpha[i, :deg + 1])
+            assert _err(got[i, :deg + 1], ref, alpha[i, :deg + 1]) < TOL64
+        assert np.all(got[:, deg + 1:] == 7.0)        # entries beyond the degree untouched
+
+
+def test_dense_batch_bucket_above_grid_limit(thx):
+    import torch
+    rng = inputs.rng(31)
+    small = rng.integers(0, 256, 66000)                # one dense bucket, not split
+    degrees = np.concatenate([small, [3000, 4100]]).astype(np.int64)
+    print(f"[case] dense bucket members={len(small)} + 2 FFT members", flush=True)
+    flat, parts = _batch_inputs(degrees, 1.0, 5)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64, thx.FP64)
+    kinds = [bk["path"] for bk in bt.buckets()]
+    assert kinds.count(3) == 1, bt.buckets()
+    a = _dev(flat)
+    b = torch.full_like(a, float("nan"))
+    bt.execute(a, b, graph=True)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    pick = list(rng.integers(0, len(small), 48)) + [len(degrees) - 2, len(degrees) - 1]
+    for i in pick:
+        al = parts[i]
+        o = int(bt.offsets[i])
+        assert _err(got[o:o + len(al)], oracle.matvec("leg2cheb", al), al) < TOL64, i
+    assert np.all(np.isfinite(got))
+
+
+# ---------------------------------------------------------------------------
 # Jacobi conversions (Sec. 5.3): case 2 stages, reflection, Chebyshev ends
 # ---------------------------------------------------------------------------
 
@@ -380,6 +451,15 @@ def _jac_scale(kind, N, params):
     (3, (-0.5, -0.75, -0.25, -0.75), 900, 0, 2),               # case 3: a + b <= -1
     (6, (-0.25, 0.5), 2500, 0, 0),
     (3, (-0.5, 0.3, 1.5, 0.3), 1100, 0, 0),                    # case 1: integer step up (banded)
+    # dense path (flags 0 below degree 512): the two-stage product, the
+    # reflection, the normalisations and the special rows materialised
+    (3, (0.0, 0.5 ** 0.5, -0.25, 0.5 ** 0.5), 300, 0, 0),
+    (5, (0.5, -0.25), 255, 1, 0),
+    (6, (0.5, -0.25), 400, 0, 0),
+    (5, (-0.5, -0.5), 100, 0, 0),
+    (3, (-0.5, -0.75, -0.25, -0.75), 300, 0, 0),
+    (3, (-0.5, 0.3, 1.5, 0.3), 200, 0, 0),
+    (5, (0.5, -0.25), 255, 0, 4),                              # entry by entry
 ])
 def test_jacobi(thx, kind, params, N, prec, flags):
     import torch
@@ -397,6 +477,8 @@ def test_jacobi(thx, kind, params, N, prec, flags):
     print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} err={err:.3e} scale={scale:.3g}", flush=True)
     assert np.all(np.isfinite(got))
     assert err < (TOL64 if prec == 0 else TOL32) * scale
+    if flags == 0 and N + 1 <= 512:
+        assert plan.path == 3
 
 
 def _cheb_eval(c, x):
