@@ -41,6 +41,10 @@ def parse():
                     help="run only the headline timed loop (for profiler runs)")
     ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
+    ap.add_argument("--only", choices=["batched", "config5"], default=None,
+                    help="run one secondary section only (profiler runs) and print its JSON")
+    ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
+                    help="with --only config5: one conversion only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 512 MiB (bandwidth ceiling and the "
                          "reference for HBM byte counters)")
@@ -108,6 +112,104 @@ def sampled_error(oracle, kind, alpha, got, rows):
     return float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
 
 
+def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bulk")):
+    """Mixed-degree batch: 4096 polynomials, degrees log-uniform in [16, 65536]."""
+    degs = inputs.batch_degrees(4096, 16, 65536, seed=4)
+    batch_res = {}
+    for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
+        if pname not in precs:
+            continue
+        flat = np.concatenate([inputs.coeffs(int(n), 1.0, seed=1000 + i) for i, n in enumerate(degs)])
+        ab = torch.from_numpy(flat).to(dev)
+        bb = torch.empty_like(ab)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt = thx.Batch(thx.LEG2CHEB, degs, tolh, prec)
+        torch.cuda.synchronize()
+        bplan_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(2):
+            bt.execute(ab, bb, graph=True)
+        torch.cuda.synchronize()
+        reps = max(3, steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bt.execute(ab, bb, graph=True)
+        torch.cuda.synchronize()
+        bms = (time.perf_counter() - t0) * 1e3 / reps
+        got = bb.cpu().numpy()
+        g = inputs.rng(5)
+        worst = 0.0
+        for i in g.choice(len(degs), size=24, replace=False):
+            o, n = int(bt.offsets[i]), int(degs[i])
+            al = flat[o:o + n + 1]
+            r = inputs.sample_rows(n, 64, seed=int(i))
+            worst = max(worst, sampled_error(oracle, "leg2cheb", al, got[o:o + n + 1], r))
+        batch_res[pname] = {"coeffs_per_s": round(bt.coefficients / (bms * 1e-3), 1), "ms_per_batch": round(bms, 4),
+                            "plan_ms": round(bplan_ms, 1), "buckets": bt.buckets(),
+                            "max_err_over_l1_sampled": worst, "hankel_tol": tolh}
+        del bt, ab, bb
+    batch_res["workload"] = ("4096 polynomials, degrees floor(exp(U[ln 16, ln 65536])) seed 4 "
+                             f"(sum of degree+1 = {int(np.sum(degs + 1))}), alpha_k ~ N(0,1)(k+1)^-1, "
+                             "hipGraph replay, plans reused")
+    return batch_res
+
+
+def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2cheb"),
+                precs=("fp64", "fp32_bulk")):
+    """65536 x degree 255 + 64 x degree 2^18 in one batch, ultraspherical and Jacobi."""
+    degs5 = np.array([255] * 65536 + [1 << 18] * 64, dtype=np.int64)
+    offs5 = np.concatenate([[0], np.cumsum(degs5 + 1)])
+    g5 = inputs.rng(55)
+    z5 = g5.standard_normal(int(offs5[-1]))
+    kidx = np.arange(int(offs5[-1])) - np.repeat(offs5[:-1], degs5 + 1)
+    flat5 = z5 / (kidx + 1.0)                      # alpha_k ~ N(0,1) (k+1)^-1 per member
+    a5 = torch.from_numpy(flat5).to(dev)
+    b5 = torch.empty_like(a5)
+    conf5 = {}
+    for short, kname, kind, params in (("ultra", "ultra_1.5_to_0.5", thx.ULTRA2ULTRA, (1.5, 0.5)),
+                                       ("jac2cheb", "jac2cheb_0.5_-0.25", thx.JAC2CHEB, (0.5, -0.25))):
+        if short not in kinds:
+            continue
+        for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
+            if pname not in precs:
+                continue
+            bt = thx.Batch(kind, degs5, tolh, prec, params=params)
+            for _ in range(2):
+                bt.execute(a5, b5, graph=True)
+            torch.cuda.synchronize()
+            reps = max(3, steps // 5)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bt.execute(a5, b5, graph=True)
+            torch.cuda.synchronize()
+            ms5 = (time.perf_counter() - t0) * 1e3 / reps
+            got = b5.cpu().numpy()
+            worst = 0.0
+            for i in list(range(0, 65536, 8191)) + [65536, 65599]:
+                o, n = int(offs5[i]), int(degs5[i])
+                al, gi = flat5[o:o + n + 1], got[o:o + n + 1]
+                if kind == thx.ULTRA2ULTRA:
+                    r = None if n <= 4096 else inputs.sample_rows(n, 32, seed=i)
+                    ref = oracle.matvec("ultra2ultra", al, params, rows=r)
+                    e = np.max(np.abs((gi if r is None else gi[r]) - ref)) / np.sum(np.abs(al))
+                    e /= max(1.0, 2.0 * n + 1.0)   # entries grow like 2j+1 for 3/2 -> 1/2
+                elif n <= 4096:
+                    e = np.max(np.abs(gi - oracle.jac2cheb(al, *params))) / np.sum(np.abs(al))
+                else:
+                    e = None
+                if e is not None:
+                    worst = max(worst, float(e))
+            conf5[f"{kname}_{pname}"] = {"coeffs_per_s": round(bt.coefficients / (ms5 * 1e-3), 1),
+                                         "ms_per_batch": round(ms5, 4), "buckets": bt.buckets(),
+                                         "max_err_over_l1_sampled": worst}
+            del bt
+    conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
+                         "N(0,1)(k+1)^-1 seed 55, hipGraph replay; ultraspherical errors divided by the "
+                         "entry growth 2N+1; Jacobi checked on the degree-255 members")
+    del a5, b5
+    return conf5
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -138,6 +240,16 @@ def main():
 
     import oracle
 
+    if args.only:
+        precs = ("fp64",) if args.prec == "fp64" else ("fp32_bulk",)
+        if args.only == "batched":
+            res = run_batched(thx, torch, inputs, oracle, dev, args.steps, precs=precs)
+        else:
+            kinds = (args.kind,) if args.kind else ("ultra", "jac2cheb")
+            res = run_config5(thx, torch, inputs, oracle, dev, args.steps, kinds=kinds, precs=precs)
+        print(json.dumps({"only": args.only, **res}), flush=True)
+        return
+
     # ---- plan (Fig. 1 steps 1-2 + symbol FFT), timed cold ----
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -157,10 +269,9 @@ def main():
     dom = max(tim.items(), key=lambda kv: kv[1][0])
     dname, (dtot, dcount) = dom
     davg_ms = dtot / dcount
-    # partial-sum groups of the inverse column pass (as chosen by the library)
-    L1 = 4096
-    L2 = L // L1 if L > L1 else 1
-    TC = min(64, 4096 // max(L2, 1))
+    # partial-sum groups of the inverse column pass (the library's rule:
+    # about 1024 workgroups over the column tiles)
+    L1, L2, TC = plan.fft_geometry()
     tiles = L1 // TC
     Gc = min(S, max(1, -(-1024 // tiles)))
     spg = -(-S // Gc)
@@ -190,90 +301,8 @@ def main():
     Kc = planc.rank
     del planc
 
-    # ---- mixed-degree batch: 4096 polynomials, degrees log-uniform in [16, 65536] ----
-    degs = inputs.batch_degrees(4096, 16, 65536, seed=4)
-    batch_res = {}
-    for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
-        flat = np.concatenate([inputs.coeffs(int(n), 1.0, seed=1000 + i) for i, n in enumerate(degs)])
-        ab = torch.from_numpy(flat).to(dev)
-        bb = torch.empty_like(ab)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        bt = thx.Batch(thx.LEG2CHEB, degs, tolh, prec)
-        torch.cuda.synchronize()
-        bplan_ms = (time.perf_counter() - t0) * 1e3
-        for _ in range(2):
-            bt.execute(ab, bb, graph=True)
-        torch.cuda.synchronize()
-        reps = max(3, args.steps // 5)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            bt.execute(ab, bb, graph=True)
-        torch.cuda.synchronize()
-        bms = (time.perf_counter() - t0) * 1e3 / reps
-        got = bb.cpu().numpy()
-        g = inputs.rng(5)
-        worst = 0.0
-        for i in g.choice(len(degs), size=24, replace=False):
-            o, n = int(bt.offsets[i]), int(degs[i])
-            al = flat[o:o + n + 1]
-            r = inputs.sample_rows(n, 64, seed=int(i))
-            worst = max(worst, sampled_error(oracle, "leg2cheb", al, got[o:o + n + 1], r))
-        batch_res[pname] = {"coeffs_per_s": round(bt.coefficients / (bms * 1e-3), 1), "ms_per_batch": round(bms, 4),
-                            "plan_ms": round(bplan_ms, 1), "buckets": len(bt.buckets()),
-                            "max_err_over_l1_sampled": worst, "hankel_tol": tolh}
-        del bt, ab, bb
-    batch_res["workload"] = ("4096 polynomials, degrees floor(exp(U[ln 16, ln 65536])) seed 4 "
-                             f"(sum of degree+1 = {int(np.sum(degs + 1))}), alpha_k ~ N(0,1)(k+1)^-1, "
-                             "hipGraph replay, plans reused")
-
-    # ---- config 5: 65536 x degree 255 + 64 x degree 2^18, ultraspherical and Jacobi ----
-    degs5 = np.array([255] * 65536 + [1 << 18] * 64, dtype=np.int64)
-    offs5 = np.concatenate([[0], np.cumsum(degs5 + 1)])
-    g5 = inputs.rng(55)
-    z5 = g5.standard_normal(int(offs5[-1]))
-    kidx = np.arange(int(offs5[-1])) - np.repeat(offs5[:-1], degs5 + 1)
-    flat5 = z5 / (kidx + 1.0)                      # alpha_k ~ N(0,1) (k+1)^-1 per member
-    a5 = torch.from_numpy(flat5).to(dev)
-    b5 = torch.empty_like(a5)
-    conf5 = {}
-    for kname, kind, params in (("ultra_1.5_to_0.5", thx.ULTRA2ULTRA, (1.5, 0.5)),
-                                ("jac2cheb_0.5_-0.25", thx.JAC2CHEB, (0.5, -0.25))):
-        for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
-            bt = thx.Batch(kind, degs5, tolh, prec, params=params)
-            for _ in range(2):
-                bt.execute(a5, b5, graph=True)
-            torch.cuda.synchronize()
-            reps = max(3, args.steps // 5)
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                bt.execute(a5, b5, graph=True)
-            torch.cuda.synchronize()
-            ms5 = (time.perf_counter() - t0) * 1e3 / reps
-            got = b5.cpu().numpy()
-            worst = 0.0
-            for i in list(range(0, 65536, 8191)) + [65536, 65599]:
-                o, n = int(offs5[i]), int(degs5[i])
-                al, gi = flat5[o:o + n + 1], got[o:o + n + 1]
-                if kind == thx.ULTRA2ULTRA:
-                    r = None if n <= 4096 else inputs.sample_rows(n, 32, seed=i)
-                    ref = oracle.matvec("ultra2ultra", al, params, rows=r)
-                    e = np.max(np.abs((gi if r is None else gi[r]) - ref)) / np.sum(np.abs(al))
-                    e /= max(1.0, 2.0 * n + 1.0)   # entries grow like 2j+1 for 3/2 -> 1/2
-                elif n <= 4096:
-                    e = np.max(np.abs(gi - oracle.jac2cheb(al, *params))) / np.sum(np.abs(al))
-                else:
-                    e = None
-                if e is not None:
-                    worst = max(worst, float(e))
-            conf5[f"{kname}_{pname}"] = {"coeffs_per_s": round(bt.coefficients / (ms5 * 1e-3), 1),
-                                         "ms_per_batch": round(ms5, 4), "buckets": bt.buckets(),
-                                         "max_err_over_l1_sampled": worst}
-            del bt
-    conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
-                         "N(0,1)(k+1)^-1 seed 55, hipGraph replay; ultraspherical errors divided by the "
-                         "entry growth 2N+1; Jacobi checked on the degree-255 members")
-    del a5, b5
+    batch_res = run_batched(thx, torch, inputs, oracle, dev, args.steps)
+    conf5 = run_config5(thx, torch, inputs, oracle, dev, args.steps)
 
     copy_gbs = copy_bandwidth(torch)
 

@@ -113,6 +113,12 @@ int32_t thx_plan_rank(const thx_plan *plan);
 int32_t thx_plan_rank_part(const thx_plan *plan, int part);
 int64_t thx_plan_fft_length(const thx_plan *plan);
 int32_t thx_plan_path(const thx_plan *plan);
+/* Three-pass geometry of the (first) stage: L = rows * cols, a row of `rows`
+ * points per row-pass workgroup, column tiles of `tile_cols` adjacent columns
+ * per column-pass workgroup.  THX_INVALID_ARGUMENT unless thx_plan_path is 2;
+ * any output pointer may be NULL. */
+thx_status thx_plan_fft_geometry(const thx_plan *plan, int64_t *rows, int64_t *cols,
+                                 int64_t *tile_cols);
 /* Largest residual diagonal entry of part `part` at termination, relative to
  * max diag(H) (the achieved pivoted-Cholesky tolerance). */
 double thx_plan_achieved_tol(const thx_plan *plan, int part);

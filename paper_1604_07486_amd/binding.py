@@ -27,6 +27,7 @@ STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_
 
 _i64, _i32, _dbl, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
+_p64 = ctypes.POINTER(ctypes.c_int64)
 
 
 def _sig(name, res, *args):
@@ -44,6 +45,7 @@ _sig("thx_plan_rank", _i32, _vp)
 _sig("thx_plan_rank_part", _i32, _vp, ctypes.c_int)
 _sig("thx_plan_fft_length", _i64, _vp)
 _sig("thx_plan_path", _i32, _vp)
+_sig("thx_plan_fft_geometry", ctypes.c_int, _vp, _p64, _p64, _p64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
      ctypes.POINTER(_i64), _vp)
@@ -123,6 +125,13 @@ class Plan:
     rank = property(lambda self: _lib.thx_plan_rank(self._h))
     fft_length = property(lambda self: _lib.thx_plan_fft_length(self._h))
     path = property(lambda self: _lib.thx_plan_path(self._h))
+
+    def fft_geometry(self):
+        """(rows, cols, tile_cols) of the three-pass FFT (path 2 only)."""
+        r, c, t = _i64(), _i64(), _i64()
+        _check(_lib.thx_plan_fft_geometry(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(t)),
+               "thx_plan_fft_geometry")
+        return r.value, c.value, t.value
 
     def rank_part(self, part: int) -> int:
         return _lib.thx_plan_rank_part(self._h, part)

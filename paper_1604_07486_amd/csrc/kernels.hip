@@ -603,82 +603,99 @@ void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s)
 // The matrix is an O(N^2) object anyway below the FFT crossover; materialised
 // once per plan, every execution is a contraction over k on the matrix cores:
 //   C[b][j] = sum_k alpha[b][k] At[k][j],   At[k][j] = A[j][k] = 0 for k < j.
-// Workgroup: 64 vectors x one chunk of up to 256 outputs; wave w owns the
-// 16-column output tiles w, w+4, w+8, w+12 (interleaved so that the triangular
-// work is balanced).  The alpha tile goes through LDS in chunks of 32 k; the
-// matrix operand is read straight from global memory (small, cache-resident).
+// Workgroup: 64 vectors x one chunk of up to 256 outputs; wave w owns vectors
+// 16w..16w+15 and all sixteen 16-column output tiles, so every wave has the
+// same (triangular) work between two barriers.  Chunks of 16 k of both
+// operands go through LDS; the next
+// chunk is read into registers while the matrix cores work on the current one.
 // v_mfma_f64_16x16x4f64 lane layout: operand a = X[m = lane&15][k = lane>>4],
 // operand b = Y[k = lane>>4][n = lane&15], result element i of a lane is
 // D[(lane>>4) + 4i][lane&15].
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int DN_BM = 64, DN_BN = 256, DN_BK = 32, DN_LDW = DN_BK + 1, DN_NT = 256;
-static_assert(DENSE_PAD % DN_BK == 0 && DN_BN % DN_BK == 0, "dense tiling");
+constexpr int DN_BM = 64, DN_BN = 256, DN_BK = 16, DN_NT = 256;
+constexpr int DN_XW = DN_BK + 1;                // alpha tile row stride (doubles)
+constexpr int DN_AW = DN_BN + 16;               // matrix tile row stride: rows alternate LDS bank halves
+constexpr int DN_XL = DN_BM * DN_BK / DN_NT;    // alpha values per thread per chunk
+constexpr int DN_AL = DN_BK * DN_BN / DN_NT;    // matrix values per thread per chunk
+static_assert(DENSE_PAD % DN_BK == 0 && DN_BN % DN_BK == 0 && DN_XL * DN_NT == DN_BM * DN_BK, "dense tiling");
 
 __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
                                                  const double *__restrict__ alpha, int64_t ld,
                                                  double *__restrict__ beta, int64_t N0, int64_t batch)
 {
-    __shared__ double xs[DN_BM * DN_LDW];
+    __shared__ double xs[DN_BM * DN_XW];
+    __shared__ double as[DN_BK * DN_AW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * DN_BM;
     const int j0 = blockIdx.y * DN_BN;
     const int jend = min(npad, j0 + DN_BN);
-    // loader: column c of the chunk, rows r0 + 8e
-    constexpr int LR = DN_BM * DN_BK / DN_NT; // 8 rows per thread
-    const int c = threadIdx.x % DN_BK, r0 = threadIdx.x / DN_BK;
-    int64_t lbase[LR], ln[LR];
+    // alpha loader: chunk column xc, vector rows xr0 + 16 e
+    const int xc = threadIdx.x % DN_BK, xr0 = threadIdx.x / DN_BK;
+    int64_t lbase[DN_XL], ln[DN_XL];
 #pragma unroll
-    for (int e = 0; e < LR; ++e) {
-        const int64_t b = b0 + r0 + 8 * e;
+    for (int e = 0; e < DN_XL; ++e) {
+        const int64_t b = b0 + xr0 + (DN_NT / DN_BK) * e;
         if (b < batch) vec_of(vr, b, ld, N0, lbase[e], ln[e]);
         else lbase[e] = 0, ln[e] = -1;
     }
-    v4d acc[4][4];
+    // matrix loader: output column j0 + threadIdx.x of chunk rows kc + e
+    const int aj = j0 + (int)threadIdx.x;
+    double xreg[DN_XL], areg[DN_AL];
+    auto fetch = [&](int kc) {
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+        for (int e = 0; e < DN_XL; ++e) {
+            const int64_t k = kc + xc;
+            xreg[e] = k <= ln[e] ? alpha[lbase[e] + k] : 0.0;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[mt][u] = v4d{0, 0, 0, 0};
-    // At[k][j] = 0 for k < j, so the chunk starting at output j0 needs k >= j0 only
+        for (int e = 0; e < DN_AL; ++e) {
+            const int k = kc + e;
+            // At[k][j] = 0 for j > k
+            areg[e] = (aj < npad && aj <= k) ? At[(int64_t)k * npad + aj] : 0.0;
+        }
+    };
+    constexpr int NTL = DN_BN / 16; // output tiles per chunk
+    v4d acc[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) acc[t] = v4d{0, 0, 0, 0};
+    // the chunk starting at output j0 needs k >= j0 only
+    fetch(j0);
     for (int kc = j0; kc < npad; kc += DN_BK) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < LR; ++e) {
-            const int64_t k = kc + c;
-            xs[(r0 + 8 * e) * DN_LDW + c] = k <= ln[e] ? alpha[lbase[e] + k] : 0.0;
-        }
+        for (int e = 0; e < DN_XL; ++e) xs[(xr0 + (DN_NT / DN_BK) * e) * DN_XW + xc] = xreg[e];
+#pragma unroll
+        for (int e = 0; e < DN_AL; ++e) as[e * DN_AW + threadIdx.x] = areg[e];
         __syncthreads();
+        if (kc + DN_BK < npad) fetch(kc + DN_BK);
 #pragma unroll
         for (int ks = 0; ks < DN_BK; ks += 4) {
             const int k0 = kc + ks;
-            double a[4];
+            const double a = xs[(16 * w + (lane & 15)) * DN_XW + ks + (lane >> 4)];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) a[mt] = xs[(16 * mt + (lane & 15)) * DN_LDW + ks + (lane >> 4)];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int jt = j0 + 16 * (w + 4 * u);
-                if (jt >= jend || k0 + 4 <= jt) continue; // outside the matrix, or all of At zero there
-                const double bv = At[(int64_t)(k0 + (lane >> 4)) * npad + jt + (lane & 15)];
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-                    acc[mt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mt], bv, acc[mt][u], 0, 0, 0);
+            for (int t = 0; t < NTL; ++t) {
+                const int jl = 16 * t;
+                if (j0 + jl >= jend || k0 + 4 <= j0 + jl) continue; // outside the matrix, or all zero there
+                const double bv = as[(ks + (lane >> 4)) * DN_AW + jl + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
             }
         }
     }
+    int64_t sbase[4], sn[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int jt = j0 + 16 * (w + 4 * u);
+    for (int i = 0; i < 4; ++i) {
+        const int64_t b = b0 + 16 * w + (lane >> 4) + 4 * i;
+        if (b < batch) vec_of(vr, b, ld, N0, sbase[i], sn[i]);
+        else sbase[i] = 0, sn[i] = -1;
+    }
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+        const int jt = j0 + 16 * t;
         if (jt >= jend) continue;
         const int64_t j = jt + (lane & 15);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t b = b0 + 16 * mt + (lane >> 4) + 4 * i;
-                if (b >= batch) continue;
-                int64_t base, n;
-                vec_of(vr, b, ld, N0, base, n);
-                if (j <= n) beta[base + j] = acc[mt][u][i];
-            }
+        for (int i = 0; i < 4; ++i)
+            if (j <= sn[i]) beta[sbase[i] + j] = acc[t][i];
     }
 }
 
@@ -941,6 +958,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
 }
 
 // the row pass keeps radix 16: two LDS exchanges per transform instead of three
+// (radix 8 with twice the waves per row measured slower)
 constexpr int RMAX_ROW = 16;
 template <typename T, int L1>
 constexpr int p2_threads() { return fft_threads(L1, 1, RMAX_ROW); }

@@ -136,7 +136,9 @@ struct thx_plan {
     int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense
     double *dense = nullptr; // path 3: At[k][j] = A[j][k], stride dense_ld
     int64_t dense_ld = 0;
-    int64_t nc = 0; // complex lanes
+    int64_t nc = 0;  // complex lanes
+    int64_t ncs = 0; // lane stride of the Cholesky columns, packed input and partial sums:
+                     // nc rounded up to 128 bytes so that column tiles never straddle lines
     int parts = 0;
     int64_t npart[2] = {0, 0}, a0[2] = {0, 0};
     int64_t L = 0;
@@ -354,19 +356,19 @@ void run_pchol(thx_plan *p, hipStream_t s)
     const int64_t maxn = std::max(p->npart[0] - p->a0[0], p->parts == 2 ? p->npart[1] - p->a0[1] : 0);
     int kcap = (int)std::min<int64_t>(KMAX, std::max<int64_t>(maxn, 1));
     p->slots_alloc = p->parts == 2 ? kcap : (kcap + 1) / 2;
-    p->ell64 = dalloc<double>(2 * (int64_t)p->slots_alloc * p->nc);
-    hip_check(hipMemsetAsync(p->ell64, 0, sizeof(double) * 2 * (size_t)p->slots_alloc * p->nc, s));
-    double *d = dalloc<double>((int64_t)p->parts * p->nc);
+    p->ell64 = dalloc<double>(2 * (int64_t)p->slots_alloc * p->ncs);
+    hip_check(hipMemsetAsync(p->ell64, 0, sizeof(double) * 2 * (size_t)p->slots_alloc * p->ncs, s));
+    double *d = dalloc<double>((int64_t)p->parts * p->ncs);
     PcholState *st = dalloc<PcholState>(1);
     hip_check(hipMemsetAsync(st, 0, sizeof(PcholState), s));
-    const int nblk = (int)((p->nc + 255) / 256);
+    const int nblk = (int)((p->ncs + 255) / 256);
     double *pv = dalloc<double>((int64_t)p->parts * nblk);
     int *pi = dalloc<int>((int64_t)p->parts * nblk);
     PcholArgs a{};
     a.hk = p->hk;
     a.d = d;
     a.ell = p->ell64;
-    a.nc = p->nc;
+    a.nc = p->ncs;
     for (int q = 0; q < 2; ++q) {
         a.n[q] = p->npart[q];
         a.a0[q] = p->a0[q];
@@ -416,8 +418,8 @@ void build_fft(thx_plan *p, hipStream_t s)
     run_pchol(p, s);
     const bool f64 = p->prec == THX_FP64;
     if (!f64) {
-        p->ell32 = dalloc<float>(2 * (int64_t)std::max(p->S, 1) * p->nc);
-        launch_cast(p->ell64, p->ell32, 2 * (int64_t)p->S * p->nc, s);
+        p->ell32 = dalloc<float>(2 * (int64_t)std::max(p->S, 1) * p->ncs);
+        launch_cast(p->ell64, p->ell32, 2 * (int64_t)p->S * p->ncs, s);
         launch_check();
     }
     double *spec = symbol_spectrum64(p, s); // natural order, scaled by 1/L
@@ -639,6 +641,7 @@ thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const 
     if (p->kd.parity) {
         p->parts = 2;
         p->nc = degree / 2 + 1;
+        p->ncs = (p->nc + 15) / 16 * 16;
         p->npart[0] = degree / 2 + 1;
         p->npart[1] = (degree + 1) / 2;
         p->a0[0] = (kind == THX_CHEB2LEG) ? 1 : 0;
@@ -646,6 +649,7 @@ thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const 
     } else {
         p->parts = 1;
         p->nc = degree + 1;
+        p->ncs = (p->nc + 15) / 16 * 16;
         p->npart[0] = degree + 1;
         p->a0[0] = (jac && jac_case3(*jac)) ? 1 : 0;
     }
@@ -716,9 +720,9 @@ void ensure_workspace(thx_plan *p, int64_t batch)
     p->row0 = nullptr;
     p->ws_batch = 0;
     const size_t es = p->esize();
-    p->X = dalloc<char>((int64_t)(es * (size_t)(batch * p->nc)));
+    p->X = dalloc<char>((int64_t)(es * (size_t)(batch * p->ncs)));
     p->Gmax = std::max(1, p->S);
-    p->Wp = dalloc<char>((int64_t)(es * (size_t)((int64_t)p->Gmax * batch * p->nc)));
+    p->Wp = dalloc<char>((int64_t)(es * (size_t)((int64_t)p->Gmax * batch * p->ncs)));
     p->row0 = dalloc<double>(batch);
     if (p->path == 2) {
         // slot chunk so that the FFT intermediates stay within ~2 GiB
@@ -740,7 +744,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
     {
         PhaseTimer t(p, THX_PHASE_PACK, s);
-        launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, p->X, p->nc, s);
+        launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, p->X, p->ncs, s);
     }
     int G = 0;
     if (p->S > 0) {
@@ -749,7 +753,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
             PhaseTimer t(p, THX_PHASE_TOEP_LDS, s);
-            if (!launch_toep_lds<T>(p->L, p->X, p->nc, n, ell, p->S, spg, G, p->that, p->twL, p->Wp, batch, s))
+            if (!launch_toep_lds<T>(p->L, p->X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL, p->Wp, batch, s))
                 throw HipFail{hipErrorInvalidValue};
         } else {
             const MultiPassGeom &g = p->geom;
@@ -758,7 +762,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
                 const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
                 {
                     PhaseTimer t(p, THX_PHASE_COL_FWD, s);
-                    if (!launch_mp_p1<T>(g, p->X, p->nc, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
+                    if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
                 {
@@ -771,14 +775,14 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
                 Gc = (ns + spg - 1) / spg;
                 {
                     PhaseTimer t(p, THX_PHASE_COL_INV, s);
-                    if (!launch_mp_p3<T>(g, p->U, p->nc, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
+                    if (!launch_mp_p3<T>(g, p->U, p->ncs, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
                 G += Gc;
             }
         }
     } else {
-        launch_zero(p->Wp, (int64_t)(p->esize() * (size_t)(batch * p->nc)), s);
+        launch_zero(p->Wp, (int64_t)(p->esize() * (size_t)(batch * p->ncs)), s);
         G = 1;
     }
     const double *row0 = nullptr;
@@ -789,7 +793,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     }
     {
         PhaseTimer t(p, THX_PHASE_UNPACK, s);
-        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->nc, p->L, p->ell64, p->nc,
+        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->ncs, p->L, p->ell64, p->ncs,
                          p->S, p->tsym, row0, s);
     }
     launch_check();
@@ -1109,6 +1113,14 @@ int64_t thx_plan_fft_length(const thx_plan *p)
     return L;
 }
 int32_t thx_plan_path(const thx_plan *p) { return p ? p->path : -1; }
+thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols, int64_t *tile_cols)
+{
+    if (!p || p->path != 2) return THX_INVALID_ARGUMENT;
+    if (rows) *rows = p->geom.L1;
+    if (cols) *cols = p->geom.L2;
+    if (tile_cols) *tile_cols = p->geom.TC;
+    return THX_OK;
+}
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {
     if (!p || part < 0 || part >= p->parts || p->path == 0 || p->path == 3) return -1.0;
@@ -1125,13 +1137,13 @@ thx_status thx_plan_factors(const thx_plan *p, int part, double *ell, int32_t *p
         for (int r = 0; r < p->K[part]; ++r) pivots[r] = p->pivots[part][r];
     if (!ell) return THX_OK;
     try {
-        std::vector<double> h(2 * (size_t)p->slots_alloc * p->nc);
+        std::vector<double> h(2 * (size_t)p->slots_alloc * p->ncs);
         hip_check(hipMemcpyAsync(h.data(), p->ell64, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream));
         hip_check(hipStreamSynchronize(stream));
         for (int r = 0; r < p->K[part]; ++r)
             for (int64_t i = 0; i < n; ++i) {
-                const int64_t idx = p->parts == 2 ? 2 * ((int64_t)r * p->nc + i) + part
-                                                  : 2 * ((int64_t)(r >> 1) * p->nc + i) + (r & 1);
+                const int64_t idx = p->parts == 2 ? 2 * ((int64_t)r * p->ncs + i) + part
+                                                  : 2 * ((int64_t)(r >> 1) * p->ncs + i) + (r & 1);
                 ell[(int64_t)r * n + i] = h[idx];
             }
     } catch (const HipFail &f) {
