@@ -45,6 +45,9 @@ def parse():
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
+                    help="summarise two rocprofv3 --pmc runs of --headline-only --copy-calibration "
+                         "(FETCH_SIZE, WRITE_SIZE) into " + "profiles/<...>.txt and exit (no GPU use)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 512 MiB (bandwidth ceiling and the "
                          "reference for HBM byte counters)")
@@ -52,6 +55,88 @@ def parse():
 
 
 COPY_BYTES = 512 << 20
+
+# Measured HBM traffic of the dominant kernel (row pass of the headline plan),
+# valid only for the kernel sources it was taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_leg2cheb_N2p20_fp64_hbm_traffic.txt")
+TRAFFIC_KERNEL = "k_mp_p2<double, 2048>"
+TRAFFIC_SOURCES = ["paper_1604_07486_amd/csrc/kernels.hip", "paper_1604_07486_amd/csrc/fft_reg.hpp",
+                   "paper_1604_07486_amd/csrc/thx_device.hpp", "paper_1604_07486_amd/csrc/launch.hpp",
+                   "paper_1604_07486_amd/csrc/plan.cpp"]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_dispatches(db, counter):
+    """(kernel name, value in KiB) per dispatch of one rocprofv3 --pmc database."""
+    import re
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, value from counters_collection where counter_name = ? "
+                       "order by dispatch_id", (counter,)).fetchall()
+    con.close()
+    return [(re.sub(r"\(.*", "", k).replace("void ", "").replace("thx::", ""), v) for _, k, v in rows]
+
+
+def write_traffic(fetch_db, write_db):
+    """Average FETCH_SIZE / WRITE_SIZE of the execute dispatches of the row pass, scaled by what the
+    same counters read for the 512 MiB device copy of the same run."""
+    out = {}
+    for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
+        d = pmc_dispatches(db, counter)
+        row = [v for k, v in d if k == TRAFFIC_KERNEL]
+        big = max(row)
+        row = [v for v in row if v > 0.5 * big]           # drops the plan's symbol transform
+        copy = max(v for k, v in d if "copyBuffer" in k)   # the 512 MiB calibration copy
+        out[key] = (sum(row) / len(row), len(row), (COPY_BYTES / 1024) / copy)
+    traffic = out["fetch"][0] * 1024 * out["fetch"][2] + out["write"][0] * 1024 * out["write"][2]
+    lines = [
+        "# HBM traffic of the row pass (k_mp_p2<double, 2048>), leg2cheb N=2^20 FP64 headline plan",
+        "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
+        "# execute dispatches; factors = bytes of the 512 MiB device copy in the same run / counter.",
+        "# Commands (repo root $R, from /tmp with TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc/fp64_FETCH_SIZE -o pmc -- python3 $R/bench.py "
+        "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
+        "#   rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc/fp64_WRITE_SIZE -o pmc -- python3 $R/bench.py "
+        "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
+        "#   python3 bench.py --write-traffic gpurun_out/pmc/fp64_FETCH_SIZE/pmc_results.db "
+        "gpurun_out/pmc/fp64_WRITE_SIZE/pmc_results.db",
+        f"kernel = {TRAFFIC_KERNEL}",
+        "phase = row",
+        f"fetch_kib_per_dispatch = {out['fetch'][0]:.1f}",
+        f"write_kib_per_dispatch = {out['write'][0]:.1f}",
+        f"dispatches = {out['fetch'][1]}",
+        f"fetch_factor = {out['fetch'][2]:.4f}",
+        f"write_factor = {out['write'][2]:.4f}",
+        f"traffic_bytes_per_launch = {traffic:.0f}",
+        f"source_sha256 = {source_digest()}",
+    ]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_traffic(phase):
+    """Bytes per launch from the committed counter summary, or None if it is absent, for another
+    kernel, or taken with other kernel sources."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("phase") != phase or kv.get("source_sha256") != source_digest():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def copy_bandwidth(torch, reps=20):
@@ -212,6 +297,9 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this library runs on a single GPU; --gpus must be 1 "
@@ -280,8 +368,10 @@ def main():
     roof = None
     if dbytes is not None:
         achieved = dbytes / (davg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(dname)
         roof = {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
                 "bytes_per_launch": dbytes, "avg_launch_ms": round(davg_ms, 5), "launches": dcount}
     # whole-step algorithmic bytes (all phases) over the step time
     step_bytes = sum(phase_bytes(p, es, S, nc, L, Gc) or 0 for p in ("col_fwd", "row", "col_inv")) \
