@@ -12,6 +12,7 @@
 #include "fft_reg.hpp"
 #include "thx_device.hpp"
 #include <math.h>
+#include <algorithm>
 
 namespace thx {
 
@@ -508,21 +509,27 @@ template void launch_unpack<float>(const KindDesc &, const int64_t *, const int6
 // the low-rank path and
 //   beta_0 = D1_0 sum_k t_k h(k) D2_k alpha_k   (k even only for parity kinds),
 // with the (0, 0) entry set through h(0), D2_0 by the plan.
-__global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
-                                              int64_t N0, const double *tsym, const double *hk,
-                                              double *row0)
+// Row 0 is a dot product of length N/2+1 (parity kinds) or N+1; it is split
+// over P workgroups per vector whose partial sums are then added in a fixed
+// order (deterministic, and fast at large N where one workgroup would stream
+// the tables alone).
+__global__ __launch_bounds__(256) void k_row0_part(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                                   int64_t N0, const double *tsym, const double *hk,
+                                                   int64_t chunk, double *part)
 {
     __shared__ double sm[256];
-    const int64_t b = blockIdx.x;
+    const int64_t b = blockIdx.y;
     int64_t base, N;
     vec_of(vr, b, ld, N0, base, N);
     const double *al = alpha + base;
+    const int64_t cmax = k.parity ? N / 2 : N; // last term index
+    const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(cmax + 1, c0 + chunk);
     double acc = 0.0;
     if (k.parity) {
-        for (int64_t c = threadIdx.x; 2 * c <= N; c += blockDim.x)
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x)
             acc = fma(tsym[c] * hk[c], d2_of(k, 2 * c) * al[2 * c], acc);
     } else {
-        for (int64_t c = threadIdx.x; c <= N; c += blockDim.x)
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x)
             acc = fma(tsym[c] * hk[c], d2_of(k, c) * al[c], acc);
     }
     sm[threadIdx.x] = acc;
@@ -531,14 +538,32 @@ __global__ __launch_bounds__(256) void k_row0(KindDesc k, VecRef vr, const doubl
         if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0) part[b * ROW0_PMAX + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(ROW0_PMAX) void k_row0_sum(KindDesc k, const double *part, int P, double *row0)
+{
+    __shared__ double sm[ROW0_PMAX];
+    const int64_t b = blockIdx.x;
+    sm[threadIdx.x] = (int)threadIdx.x < P ? part[b * ROW0_PMAX + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int h = ROW0_PMAX / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sm[threadIdx.x] += sm[threadIdx.x + h];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) row0[b] = d1_of(k, 0) * sm[0];
 }
 
 void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
-                          int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
-                          double *row0, hipStream_t s)
+                        int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
+                        double *part, double *row0, hipStream_t s)
 {
-    k_row0<<<(unsigned)batch, 256, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tsym, hk, row0);
+    const int64_t terms = (k.parity ? N / 2 : N) + 1;
+    const int64_t P = std::min<int64_t>(ROW0_PMAX, std::max<int64_t>(1, (terms + 2047) / 2048));
+    const int64_t chunk = (terms + P - 1) / P;
+    k_row0_part<<<dim3((unsigned)P, (unsigned)batch), 256, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tsym, hk,
+                                                                  chunk, part);
+    k_row0_sum<<<(unsigned)batch, ROW0_PMAX, 0, s>>>(k, part, (int)P, row0);
 }
 
 // ============================================================================

@@ -104,9 +104,12 @@ void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, co
                    const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc, int64_t L,
                    const double *ell64, int64_t nc_ell, int S, const double *tsym,
                    const double *row0, hipStream_t s);
+// row 0 by a direct dot product: partial sums over up to ROW0_PMAX workgroups per
+// vector into part[batch][ROW0_PMAX], then summed in a fixed order into row0[batch]
+constexpr int ROW0_PMAX = 256;
 void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
-                          int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
-                          double *row0, hipStream_t s);
+                        int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
+                        double *part, double *row0, hipStream_t s);
 
 // ---- direct O(N^2) ----------------------------------------------------------------
 void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,

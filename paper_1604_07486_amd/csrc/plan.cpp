@@ -164,6 +164,7 @@ struct thx_plan {
     int64_t ws_batch = 0;
     void *X = nullptr, *Wp = nullptr, *U = nullptr;
     double *row0 = nullptr;
+    double *row0_part = nullptr; // [batch][ROW0_PMAX] partial sums of row 0
     int64_t U_slots = 0;
     int Gmax = 0;
     // per-phase event timing
@@ -201,6 +202,7 @@ struct thx_plan {
         dfree(Wp);
         dfree(U);
         dfree(row0);
+        dfree(row0_part);
         delete[] pivots[0];
         delete[] pivots[1];
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -716,14 +718,17 @@ void ensure_workspace(thx_plan *p, int64_t batch)
     dfree(p->Wp);
     dfree(p->U);
     dfree(p->row0);
+    dfree(p->row0_part);
     p->X = p->Wp = p->U = nullptr;
     p->row0 = nullptr;
+    p->row0_part = nullptr;
     p->ws_batch = 0;
     const size_t es = p->esize();
     p->X = dalloc<char>((int64_t)(es * (size_t)(batch * p->ncs)));
     p->Gmax = std::max(1, p->S);
     p->Wp = dalloc<char>((int64_t)(es * (size_t)((int64_t)p->Gmax * batch * p->ncs)));
     p->row0 = dalloc<double>(batch);
+    if (p->row0_direct) p->row0_part = dalloc<double>(batch * ROW0_PMAX);
     if (p->path == 2) {
         // slot chunk so that the FFT intermediates stay within ~2 GiB
         const int64_t per = (int64_t)es * p->L * batch;
@@ -788,7 +793,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     const double *row0 = nullptr;
     if (p->row0_direct) {
         PhaseTimer t(p, THX_PHASE_ROW0, s);
-        launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0, s);
+        launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0_part, p->row0, s);
         row0 = p->row0;
     }
     {
