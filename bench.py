@@ -209,7 +209,7 @@ def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bul
         bb = torch.empty_like(ab)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        bt = thx.Batch(thx.LEG2CHEB, degs, tolh, prec)
+        bt = thx.Batch(thx.LEG2CHEB, degs, tolh, prec, flags=thx.FLAG_AUTOTUNE)
         torch.cuda.synchronize()
         bplan_ms = (time.perf_counter() - t0) * 1e3
         for _ in range(2):
@@ -235,7 +235,8 @@ def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bul
         del bt, ab, bb
     batch_res["workload"] = ("4096 polynomials, degrees floor(exp(U[ln 16, ln 65536])) seed 4 "
                              f"(sum of degree+1 = {int(np.sum(degs + 1))}), alpha_k ~ N(0,1)(k+1)^-1, "
-                             "hipGraph replay, plans reused")
+                             "hipGraph replay, plans reused, buckets autotuned for their member counts "
+                             "(plan_ms includes the tuning)")
     return batch_res
 
 
@@ -258,7 +259,7 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
         for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
             if pname not in precs:
                 continue
-            bt = thx.Batch(kind, degs5, tolh, prec, params=params)
+            bt = thx.Batch(kind, degs5, tolh, prec, params=params, flags=thx.FLAG_AUTOTUNE)
             for _ in range(2):
                 bt.execute(a5, b5, graph=True)
             torch.cuda.synchronize()
@@ -289,8 +290,8 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
                                          "max_err_over_l1_sampled": worst}
             del bt
     conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
-                         "N(0,1)(k+1)^-1 seed 55, hipGraph replay; ultraspherical errors divided by the "
-                         "entry growth 2N+1; Jacobi checked on the degree-255 members")
+                         "N(0,1)(k+1)^-1 seed 55, hipGraph replay, buckets autotuned; ultraspherical errors "
+                         "divided by the entry growth 2N+1; Jacobi checked on the degree-255 members")
     del a5, b5
     return conf5
 
@@ -319,6 +320,7 @@ def main():
     if args.headline_only:
         prec = thx.FP64 if args.prec == "fp64" else thx.FP32_BULK
         plan = thx.Plan(thx.LEG2CHEB, N, 1e-15 if prec == thx.FP64 else 1e-7, prec)
+        plan.autotune(1)
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
         print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
@@ -344,6 +346,10 @@ def main():
     plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    plan.autotune(1)
+    torch.cuda.synchronize()
+    tune_ms = (time.perf_counter() - t0) * 1e3
 
     ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
     value = (N + 1) / (ms * 1e-3)
@@ -379,6 +385,7 @@ def main():
 
     # ---- FP32-bulk at the same N (Lambda, Cholesky, D1/D2 in FP64) ----
     plan32 = thx.Plan(thx.LEG2CHEB, N, 1e-7, thx.FP32_BULK)
+    plan32.autotune(1)
     ms32, tim32 = time_plan(thx, torch, plan32, a, b, args.steps, args.warmup)
     err32 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
     K32 = plan32.rank
@@ -386,6 +393,7 @@ def main():
 
     # ---- Chebyshev -> Legendre at the same N (Sec. 5.1) ----
     planc = thx.Plan(thx.CHEB2LEG, N, 1e-17, thx.FP64)
+    planc.autotune(1)
     msc, _ = time_plan(thx, torch, planc, a, b, max(5, args.steps // 2), 2)
     errc = sampled_error(oracle, "cheb2leg", alpha, b.cpu().numpy(), rows)
     Kc = planc.rank
@@ -430,13 +438,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "leg2cheb N=2^20 (1048577 coefficients), batch 1, FP64 end to end, "
-                               "alpha_k ~ N(0,1)(k+1)^-1.5 seed 20, Hankel tol 1e-15, plan reused",
+                               "alpha_k ~ N(0,1)(k+1)^-1.5 seed 20, Hankel tol 1e-15, plan reused "
+                               "(autotuned for one vector)",
                    "N": N, "batch": 1, "K": S, "L": L, "path": plan.path},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": {"fp64_max_err_over_l1": err64, "fp64_bar": 1e-13,
                      "rows_checked": int(len(rows))},
         "plan_ms": round(plan_ms, 2),
+        "autotune_ms": round(tune_ms, 2),
+        "fft_geometry": list(plan.fft_geometry()) if plan.path == 2 else None,
         "copy_gbs_measured": round(copy_gbs, 1),
         "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
         "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim.items()},

@@ -62,6 +62,8 @@ typedef enum {
 #define THX_FLAG_FORCE_FFT 2u    /* never use the direct evaluation (testing)        */
 #define THX_FLAG_NO_DENSE 4u     /* direct evaluation entry by entry instead of the
                                     materialised dense matrix (testing, plan memory) */
+#define THX_FLAG_AUTOTUNE 8u     /* thx_batch_create: tune every bucket for its member
+                                    count (thx_plan_autotune); plans: no effect       */
 
 typedef struct thx_plan thx_plan;
 
@@ -119,6 +121,20 @@ int32_t thx_plan_path(const thx_plan *plan);
  * any output pointer may be NULL. */
 thx_status thx_plan_fft_geometry(const thx_plan *plan, int64_t *rows, int64_t *cols,
                                  int64_t *tile_cols);
+/* Tune a plan for executions of `batch` vectors of its degree (the launch
+ * shapes, row length and crossover that Sec. 2.1's reuse of one plan makes
+ * worth choosing once): every FFT stage times its candidate launch shapes
+ * (single-workgroup path: workgroups per launch; three-pass path: row length
+ * and workgroups of the inverse column pass), then, for degree + 1 <= 2048,
+ * the whole conversion times the stages against the materialised dense
+ * matrix (path 3) and keeps the faster.  Candidates run on zero inputs with
+ * HIP events on `stream` (median of three after a warm-up); the call
+ * allocates and synchronises, and the plan must not be executing.  Results are
+ * identical up to rounding whichever candidate wins.  THX_FLAG_FORCE_FFT or
+ * THX_FLAG_NO_DENSE at creation exclude the dense candidate.  Errors:
+ * THX_INVALID_ARGUMENT (null plan, batch < 1), THX_OUT_OF_MEMORY, THX_HIP_ERROR. */
+thx_status thx_plan_autotune(thx_plan *plan, int64_t batch, hipStream_t stream);
+
 /* Largest residual diagonal entry of part `part` at termination, relative to
  * max diag(H) (the achieved pivoted-Cholesky tolerance). */
 double thx_plan_achieved_tol(const thx_plan *plan, int part);

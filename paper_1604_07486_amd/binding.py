@@ -20,7 +20,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 # enums (include/thx.h)
 LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG, JAC2CHEB, CHEB2JAC = 0, 1, 2, 3, 4, 5, 6
 FP64, FP32_BULK = 0, 1
-FLAG_FORCE_DIRECT, FLAG_FORCE_FFT, FLAG_NO_DENSE = 1, 2, 4
+FLAG_FORCE_DIRECT, FLAG_FORCE_FFT, FLAG_NO_DENSE, FLAG_AUTOTUNE = 1, 2, 4, 8
 PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct", "dense"]
 STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_TOL_NOT_REACHED",
           4: "THX_OUT_OF_MEMORY", 5: "THX_HIP_ERROR"}
@@ -46,6 +46,7 @@ _sig("thx_plan_rank_part", _i32, _vp, ctypes.c_int)
 _sig("thx_plan_fft_length", _i64, _vp)
 _sig("thx_plan_path", _i32, _vp)
 _sig("thx_plan_fft_geometry", ctypes.c_int, _vp, _p64, _p64, _p64)
+_sig("thx_plan_autotune", ctypes.c_int, _vp, _i64, _vp)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
      ctypes.POINTER(_i64), _vp)
@@ -125,6 +126,11 @@ class Plan:
     rank = property(lambda self: _lib.thx_plan_rank(self._h))
     fft_length = property(lambda self: _lib.thx_plan_fft_length(self._h))
     path = property(lambda self: _lib.thx_plan_path(self._h))
+
+    def autotune(self, batch: int, stream=None):
+        """Choose launch shapes / dense vs FFT for executions of `batch` vectors."""
+        _check(_lib.thx_plan_autotune(self._h, int(batch), _stream(stream)), "thx_plan_autotune")
+        return self
 
     def fft_geometry(self):
         """(rows, cols, tile_cols) of the three-pass FFT (path 2 only)."""

@@ -764,9 +764,14 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
     cpx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
-    const cpx<T> *Xb = X + b * nc;
+    // In double precision the packed input, the symbol and l~_s are read again
+    // where they are used (cache hits) rather than kept live across the
+    // transforms: opaque pointers stop the loads from being hoisted out of the
+    // slot loop (fewer registers; measured faster for FP64 only).
+    auto opq = [](const cpx<T> *q) { return sizeof(T) == 8 ? opaque_ptr(q) : q; };
     for (int s = s0; s < s1; ++s) {
-        const cpx<T> *es = ell + (int64_t)s * nc;
+        const cpx<T> *es = opq(ell + (int64_t)s * nc);
+        const cpx<T> *Xb = opq(X + b * nc);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int pos, c;
@@ -774,13 +779,15 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
             v[e] = pos < n ? cdiag(es[pos], Xb[pos]) : cpx<T>{0, 0};
         }
         F::forward(v, lds, tw);
+        const cpx<T> *ts = opq(that);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int pos, c;
             F::out_pos(e, pos, c);
-            v[e] = cmul(v[e], that[pos]);
+            v[e] = cmul(v[e], ts[pos]);
         }
         F::inverse(v, lds, tw);
+        es = opq(es);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int pos, c;

@@ -123,13 +123,16 @@ void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s);
 // At[k][j] = A[j][k], row-major with stride npad (a multiple of DENSE_PAD), zero
 // outside 0..N and for k < j (A upper triangular).  off / deg as for pack.
 constexpr int64_t DENSE_PAD = 32;
-constexpr int64_t DENSE_MAX = 512; // largest degree + 1 with a materialised matrix
+constexpr int64_t DENSE_MAX = 512;       // largest degree + 1 materialised by default
+constexpr int64_t DENSE_TUNE_MAX = 2048; // largest degree + 1 the autotuner tries it for
 void launch_dense(const double *At, int64_t npad, const int64_t *off, const int64_t *deg,
                   const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
                   hipStream_t s);
 
 // ---- a5: Toeplitz products ---------------------------------------------------------
-// Largest length handled by one workgroup in LDS.
+// Largest length handled by one workgroup in LDS.  (Twice that, one workgroup
+// per CU in 136 KiB, was measured slower than the three passes at every batch
+// size.)
 template <typename T> constexpr int64_t lds_max_len() { return sizeof(T) == 8 ? 4096 : 8192; }
 // Row lengths of the three-pass scheme.  The short row takes half the LDS of
 // the long one, so twice as many row workgroups share a CU and the loads,

@@ -134,8 +134,11 @@ struct thx_plan {
     uint32_t flags = 0;
     KindDesc kd{};
     int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense
-    double *dense = nullptr; // path 3: At[k][j] = A[j][k], stride dense_ld
-    int64_t dense_ld = 0;
+    double *dense = nullptr; // path 3 (reported): At[k][j] = A[j][k], stride dense_ld; the
+    int64_t dense_ld = 0;    // stages keep their own path for re-tuning
+    // launch shapes (workgroups targeted per launch), set by the autotuner
+    int lds_blocks = 512;    // single-workgroup path: slot groups x vectors
+    int p3_blocks = 1024;    // inverse column pass: column tiles x slot groups x vectors
     int64_t nc = 0;  // complex lanes
     int64_t ncs = 0; // lane stride of the Cholesky columns, packed input and partial sums:
                      // nc rounded up to 128 bytes so that column tiles never straddle lines
@@ -589,7 +592,6 @@ void build_dense(thx_plan *p, hipStream_t s)
     p->tmp_elems = 0;
     p->dense = At;
     p->dense_ld = npad;
-    p->path = 3;
 }
 
 thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
@@ -754,7 +756,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     int G = 0;
     if (p->S > 0) {
         if (p->path == 1) {
-            int Gt = (int)std::min<int64_t>(p->S, std::max<int64_t>(1, (512 + batch - 1) / batch));
+            int Gt = (int)std::min<int64_t>(p->S, std::max<int64_t>(1, (p->lds_blocks + batch - 1) / batch));
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
             PhaseTimer t(p, THX_PHASE_TOEP_LDS, s);
@@ -775,7 +777,8 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
                     if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
-                int Gc = (int)std::min<int64_t>(ns, std::max<int64_t>(1, (1024 + tiles * batch - 1) / (tiles * batch)));
+                int Gc = (int)std::min<int64_t>(
+                    ns, std::max<int64_t>(1, (p->p3_blocks + tiles * batch - 1) / (tiles * batch)));
                 const int spg = (ns + Gc - 1) / Gc;
                 Gc = (ns + spg - 1) / spg;
                 {
@@ -869,6 +872,148 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     } catch (const std::bad_alloc &) {
         return THX_OUT_OF_MEMORY;
     }
+    return THX_OK;
+}
+
+// ---- autotuning: launch shapes, row length, dense vs FFT ------------------------
+// Candidates are timed with HIP events on zero-filled inputs of the expected
+// batch (values do not change the work), median of three after one warm-up.
+template <typename F>
+float time_launches(F &&run, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0));
+    hip_check(hipEventCreate(&e1));
+    float t[3];
+    try {
+        run();
+        for (float &x : t) {
+            hip_check(hipEventRecord(e0, s));
+            run();
+            hip_check(hipEventRecord(e1, s));
+            hip_check(hipEventSynchronize(e1));
+            hip_check(hipEventElapsedTime(&x, e0, e1));
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    hip_check(hipEventDestroy(e0));
+    hip_check(hipEventDestroy(e1));
+    std::sort(t, t + 3);
+    return t[1];
+}
+
+// rebuild the three-pass tables (row length `row`) from a fresh double spectrum
+void configure_rows(thx_plan *p, int64_t row, hipStream_t s)
+{
+    const bool f64 = p->prec == THX_FP64;
+    const MultiPassGeom g = f64 ? multipass_geom<double>(p->L, row) : multipass_geom<float>(p->L, row);
+    if (g.L1 == p->geom.L1) return;
+    double *spec = symbol_spectrum64(p, s);
+    dfree(p->twL1);
+    dfree(p->twL2);
+    dfree(p->twA);
+    dfree(p->that);
+    for (double *&q : p->tw64_keep) {
+        dfree(q);
+        q = nullptr;
+    }
+    p->twL1 = p->twL2 = p->twA = p->that = nullptr;
+    p->geom = g;
+    p->twL1 = make_twiddles(p, g.L1, g.L1, s, 0);
+    p->twL2 = make_twiddles(p, g.L2, g.L2, s, 1);
+    p->twA = make_twiddles(p, p->L, g.L1, s, 2);
+    p->that = dalloc<char>((int64_t)p->esize() * p->L);
+    if (f64) launch_reorder<double>(spec, p->that, p->L, g.L1, g.L2, 2, s);
+    else launch_reorder<float>(spec, p->that, p->L, g.L1, g.L2, 2, s);
+    launch_check();
+    hip_check(hipStreamSynchronize(s));
+    dfree(spec);
+}
+
+void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, hipStream_t s)
+{
+    auto run = [&] { execute_stage(p, nullptr, nullptr, alpha, beta, p->N, batch, p->N + 1, s); };
+    if (p->path == 1) {
+        int best = p->lds_blocks;
+        float tb = 1e30f;
+        for (int lb : {256, 512, 1024, 2048}) {
+            p->lds_blocks = lb;
+            const float t = time_launches(run, s);
+            if (t < tb) tb = t, best = lb;
+        }
+        p->lds_blocks = best;
+    } else if (p->path == 2) {
+        const bool f64 = p->prec == THX_FP64;
+        const int64_t rows[2] = {f64 ? mp_row_short<double>() : mp_row_short<float>(),
+                                 f64 ? mp_row_long<double>() : mp_row_long<float>()};
+        int64_t best_row = p->geom.L1;
+        int best_p3 = p->p3_blocks;
+        float tb = 1e30f;
+        for (int64_t row : rows) {
+            if (p->L / row < 2 || p->L / row > 1024) continue;
+            configure_rows(p, row, s);
+            if (p->geom.L1 != row) continue;
+            for (int p3 : {512, 1024, 2048}) {
+                p->p3_blocks = p3;
+                const float t = time_launches(run, s);
+                if (t < tb) tb = t, best_row = row, best_p3 = p3;
+            }
+        }
+        configure_rows(p, best_row, s);
+        p->p3_blocks = best_p3;
+    }
+}
+
+thx_status autotune(thx_plan *p, int64_t batch, hipStream_t s)
+{
+    if (!p || batch < 1) return THX_INVALID_ARGUMENT;
+    const int64_t n1 = p->N + 1;
+    const int64_t fb = std::min<int64_t>(batch, 65535); // the FFT launches' grid limit
+    double *a = nullptr, *b = nullptr;
+    try {
+        a = dalloc<double>(batch * n1);
+        b = dalloc<double>(batch * n1);
+        launch_zero(a, batch * n1 * (int64_t)sizeof(double), s);
+        for (thx_plan *q = p; q; q = q->next) {
+            if (q->path == 0 || p->N < 2) continue;
+            ensure_workspace(q, fb);
+            tune_stage(q, a, b, fb, s);
+        }
+        // dense product vs the stages' own paths, for the whole conversion
+        bool fft_capable = false;
+        for (const thx_plan *q = p; q; q = q->next) fft_capable |= q->path != 0;
+        if (fft_capable && !(p->flags & (THX_FLAG_FORCE_FFT | THX_FLAG_NO_DENSE)) && n1 <= DENSE_TUNE_MAX) {
+            double *keep = p->dense;
+            p->dense = nullptr;
+            const float t_fft = time_launches([&] { execute_core(p, nullptr, nullptr, a, b, p->N, fb, n1, s, fb * n1); }, s);
+            if (keep) {
+                p->dense = keep;
+            } else {
+                build_dense(p, s);
+            }
+            const float t_dense = time_launches([&] { execute_core(p, nullptr, nullptr, a, b, p->N, fb, n1, s, fb * n1); }, s);
+            if (t_fft < t_dense) {
+                dfree(p->dense);
+                p->dense = nullptr;
+                p->dense_ld = 0;
+            }
+        }
+        hip_check(hipStreamSynchronize(s));
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        dfree(a);
+        dfree(b);
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        dfree(a);
+        dfree(b);
+        return THX_OUT_OF_MEMORY;
+    }
+    dfree(a);
+    dfree(b);
     return THX_OK;
 }
 
@@ -984,7 +1129,9 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                     bk.Nmax = std::max(bk.Nmax, degrees[idx[m]]);
                 }
                 bk.members = (int64_t)ho.size();
-                const uint32_t f = (kv.first == 0 ? THX_FLAG_FORCE_DIRECT : THX_FLAG_FORCE_FFT) |
+                // with autotuning, an FFT bucket keeps its FFT plan and may still pick the dense product
+                const uint32_t f = (kv.first == 0 ? THX_FLAG_FORCE_DIRECT
+                                                  : ((flags & THX_FLAG_AUTOTUNE) ? 0u : THX_FLAG_FORCE_FFT)) |
                                    (flags & THX_FLAG_NO_DENSE);
                 thx_status st = create_plan(&bk.plan, kind, params, nparams, bk.Nmax, tol, prec, f, s);
                 if (st == THX_TOL_NOT_REACHED) result = st;
@@ -992,12 +1139,20 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                     delete b;
                     return st;
                 }
+                if (flags & THX_FLAG_AUTOTUNE) {
+                    thx_status ts = autotune(bk.plan, bk.members, s);
+                    if (ts != THX_OK) {
+                        delete bk.plan;
+                        delete b;
+                        return ts;
+                    }
+                }
                 if (!bk.plan->dense && bk.members > MAX_BUCKET_MEMBERS) {
                     delete bk.plan;
                     delete b;
                     return THX_UNSUPPORTED;
                 }
-                bk.L = (bk.plan->path == 0 || bk.plan->path == 3) ? 0 : bk.plan->L;
+                bk.L = (bk.plan->path == 0 || bk.plan->dense) ? 0 : bk.plan->L;
                 bk.d_off = dalloc<int64_t>(bk.members);
                 bk.d_deg = dalloc<int64_t>(bk.members);
                 hip_check(hipMemcpyAsync(bk.d_off, ho.data(), sizeof(int64_t) * ho.size(), hipMemcpyHostToDevice, s));
@@ -1114,13 +1269,14 @@ int64_t thx_plan_fft_length(const thx_plan *p)
 {
     if (!p) return -1;
     int64_t L = 0;
+    if (p->dense) return 0;
     for (const thx_plan *q = p; q; q = q->next) L = std::max<int64_t>(L, (q->path == 1 || q->path == 2) ? q->L : 0);
     return L;
 }
-int32_t thx_plan_path(const thx_plan *p) { return p ? p->path : -1; }
+int32_t thx_plan_path(const thx_plan *p) { return p ? (p->dense ? 3 : p->path) : -1; }
 thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols, int64_t *tile_cols)
 {
-    if (!p || p->path != 2) return THX_INVALID_ARGUMENT;
+    if (!p || p->path != 2 || p->dense) return THX_INVALID_ARGUMENT;
     if (rows) *rows = p->geom.L1;
     if (cols) *cols = p->geom.L2;
     if (tile_cols) *tile_cols = p->geom.TC;
@@ -1128,7 +1284,7 @@ thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols
 }
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {
-    if (!p || part < 0 || part >= p->parts || p->path == 0 || p->path == 3) return -1.0;
+    if (!p || part < 0 || part >= p->parts || p->path == 0) return -1.0;
     return p->dfinal[part];
 }
 
@@ -1214,6 +1370,11 @@ thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a
     return THX_OK;
 }
 
+thx_status thx_plan_autotune(thx_plan *plan, int64_t batch, hipStream_t stream)
+{
+    return autotune(plan, batch, stream);
+}
+
 thx_status thx_plan_enable_timing(thx_plan *p, int enable)
 {
     if (!p) return THX_INVALID_ARGUMENT;
@@ -1275,8 +1436,8 @@ thx_status thx_batch_bucket_info(const thx_batch *b, int i, int64_t *fft_length,
     if (fft_length) *fft_length = bk.L;
     if (members) *members = bk.members;
     if (max_degree) *max_degree = bk.Nmax;
-    if (path) *path = bk.plan->path;
-    if (rank) *rank = bk.plan->path == 0 ? 0 : bk.plan->S;
+    if (path) *path = thx_plan_path(bk.plan);
+    if (rank) *rank = thx_plan_rank(bk.plan);
     return THX_OK;
 }
 

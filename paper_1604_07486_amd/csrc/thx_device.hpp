@@ -33,6 +33,16 @@ __device__ __forceinline__ cpx<T> cdiag(cpx<T> d, cpx<T> v) { return {d.x * v.x,
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x >> 1); }
 
+// A workgroup-uniform pointer the compiler must treat as changed: loads through
+// it are not hoisted out of the enclosing loop (keeps register pressure down
+// where re-reading from cache is cheaper than holding the values).
+template <typename P>
+__device__ __forceinline__ P *opaque_ptr(P *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 // Streaming (nontemporal) access to data touched once per pass, so that L2
 // keeps the reused tiles (symbol rows, packed input).
 #ifndef THX_NT

@@ -103,6 +103,12 @@ def test_introspection_null_plan(lib):
     assert lib.thx_plan_path(None) == -1
     assert lib.thx_plan_fft_length(None) == -1
     assert lib.thx_plan_destroy(None) == 0
+    lib.thx_plan_autotune.restype = ctypes.c_int
+    lib.thx_plan_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.thx_plan_autotune(None, 4, None) == 1          # THX_INVALID_ARGUMENT
+    lib.thx_plan_fft_geometry.restype = ctypes.c_int
+    lib.thx_plan_fft_geometry.argtypes = [ctypes.c_void_p] * 4
+    assert lib.thx_plan_fft_geometry(None, None, None, None) == 1
 
 
 def test_table_rejects_negative_count(lib):

@@ -408,6 +408,58 @@ def test_dense_batch_bucket_above_grid_limit(thx):
 
 
 # ---------------------------------------------------------------------------
+# Autotuning: whichever launch shape, row length or dense/FFT choice wins the
+# timing, the results must meet the same bars.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,params,N,prec,batch", [
+    (0, (), 1500, 0, 300),          # dense vs single-workgroup FFT
+    (0, (), 20000, 0, 4),           # three-pass: row length and inverse-pass groups
+    (0, (), 9000, 1, 16),
+    (1, (), 1200, 0, 64),           # cheb2leg: row 0 direct in either path
+    (5, (0.5, -0.25), 1000, 0, 50), # two stages, reflection, normalisation
+])
+def test_autotuned_plan_matches_oracle(thx, kind, params, N, prec, batch):
+    import torch
+    print(f"[case] autotune kind={kind} N={N} prec={prec} batch={batch}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=N + batch, batch=batch)
+    plan = thx.Plan(kind, N, EPS64 if prec == 0 else EPS32, prec, params=params)
+    plan.autotune(batch)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    path = plan.path
+    geo = plan.fft_geometry() if path == 2 else None
+    print(f"  path={path} geometry={geo}", flush=True)
+    for i in (0, batch // 2, batch - 1):
+        al = alpha[i]
+        ref = _jac_ref(kind, al, params) if kind in (3, 5, 6) else oracle.matvec(ORACLE_KIND[kind], al, params)
+        bar = (TOL64 if prec == 0 else TOL32) * (_jac_scale(kind, N, params) if kind in (3, 5, 6) else 1.0)
+        assert _err(got[i], ref, al) < bar, (i, path)
+
+
+def test_autotuned_batch_graph(thx):
+    import torch
+    degrees = inputs.batch_degrees(96, 16, 12000, seed=44)
+    flat, parts = _batch_inputs(degrees, 1.0, 9)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64, thx.FP64, flags=thx.FLAG_AUTOTUNE)
+    print(f"[case] autotuned batch buckets={bt.buckets()}", flush=True)
+    a = _dev(flat)
+    eager = torch.full_like(a, float("nan"))
+    bt.execute(a, eager)
+    graph = torch.full_like(a, float("nan"))
+    bt.execute(a, graph, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(eager, graph)
+    got = eager.cpu().numpy()
+    for i, al in enumerate(parts):
+        o = int(bt.offsets[i])
+        assert _err(got[o:o + len(al)], oracle.matvec("leg2cheb", al), al) < TOL64, i
+
+
+# ---------------------------------------------------------------------------
 # Jacobi conversions (Sec. 5.3): case 2 stages, reflection, Chebyshev ends
 # ---------------------------------------------------------------------------
 
