@@ -73,17 +73,20 @@ typedef struct thx_plan thx_plan;
  * residual diagonal entry is <= tol * max diag(H); Sec. 2.1 leaves the rule
  * open), and transforms the Toeplitz symbol.  The plan may be reused for any
  * number of executions (Sec. 2.1, last paragraph).
- *   params / nparams: kind parameters -- ULTRA2ULTRA (l1, l2) with l1, l2 > 0;
- *   JAC2JAC (a, b, g, d), JAC2CHEB (a, b), CHEB2JAC (g, d), all > -1: a change
- *   of the second parameter is done first by the reflection
- *   P_k^(a,b)(-x) = (-1)^k P_k^(b,a)(x), then the first; each of these stages
- *   must be case 2 of Sec. 5.3 (|first - target| < 1 or = 1, and first +
- *   second > -1), else THX_UNSUPPORTED;  LAG2LAG (a1, a2) with a1, a2 > -1.
- *   LEG2CHEB / CHEB2LEG take none.
+ *   params / nparams: kind parameters -- ULTRA2ULTRA (l1, l2) with l1, l2 > 0
+ *   (Sec. 5.2: one stage when l1 - l2 <= 1, negative integer differences
+ *   banded (case 1); a larger drop goes down in unit steps first (case 3));
+ *   JAC2JAC (a, b, g, d), JAC2CHEB (a, b), CHEB2JAC (g, d), all > -1 (Sec.
+ *   5.3): a change of the second parameter is done first by the reflection
+ *   P_k^(a,b)(-x) = (-1)^k P_k^(b,a)(x), then the first; a parameter that
+ *   drops by more than 1 goes down in unit steps first (case 4), every stage
+ *   is then case 2 (case 1 banded for integer rises, case 3 with row 0
+ *   computed directly when first + second <= -1);  LAG2LAG (a1, a2) with
+ *   a1, a2 > -1.  LEG2CHEB / CHEB2LEG take none.
  *   degree >= 0; 0 < tol < 1; flags: THX_FLAG_*.
  * On success *out owns device memory until thx_plan_destroy.  Errors:
  * THX_INVALID_ARGUMENT (out == NULL, degree < 0, tol outside (0,1), bad params),
- * THX_UNSUPPORTED (parameters outside the implemented cases), THX_OUT_OF_MEMORY,
+ * THX_UNSUPPORTED (unknown kind), THX_OUT_OF_MEMORY,
  * THX_HIP_ERROR.  THX_TOL_NOT_REACHED returns a usable plan. */
 thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, int nparams,
                            int64_t degree, double tol, thx_precision prec, uint32_t flags,
@@ -110,7 +113,12 @@ thx_status thx_plan_destroy(thx_plan *plan);
  * FFT, 2 three-pass FFT, 3 dense: below the FFT crossover (degree + 1 <= 512,
  * THX_FLAG_NO_DENSE not set) the plan materialises the (degree+1)^2 matrix once
  * by the direct evaluation of the unit vectors, and every execution is one
- * double-precision matrix-core product with it (both precisions). */
+ * double-precision matrix-core product with it (both precisions), 4 unit step:
+ * a parameter lowered by exactly 1 makes T and H constant (Sec. 5.2 and 5.3,
+ * case 1), and beta_j = D1_j t_0 h_0 sum_{k >= j} D2_k alpha_k (k - j even for
+ * the parity kinds) is a suffix sum, computed by a reverse scan in double
+ * precision in O(N).  For a multi-stage plan, path and rank describe the first
+ * stage (path 3 the whole conversion). */
 int32_t thx_plan_rank(const thx_plan *plan);
 int32_t thx_plan_rank_part(const thx_plan *plan, int part);
 int64_t thx_plan_fft_length(const thx_plan *plan);
@@ -222,7 +230,8 @@ enum {
     THX_PHASE_UNPACK = 6,   /* beta = D1 w (Fig. 1 step 5)                          */
     THX_PHASE_DIRECT = 7,   /* O(N^2) direct evaluation                             */
     THX_PHASE_DENSE = 8,    /* product with the materialised matrix (path 3)        */
-    THX_NPHASES = 9
+    THX_PHASE_SCAN = 9,     /* unit step by suffix sums (path 4)                    */
+    THX_NPHASES = 10
 };
 thx_status thx_plan_enable_timing(thx_plan *plan, int enable);
 thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);

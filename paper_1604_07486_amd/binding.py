@@ -21,7 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG, JAC2CHEB, CHEB2JAC = 0, 1, 2, 3, 4, 5, 6
 FP64, FP32_BULK = 0, 1
 FLAG_FORCE_DIRECT, FLAG_FORCE_FFT, FLAG_NO_DENSE, FLAG_AUTOTUNE = 1, 2, 4, 8
-PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct", "dense"]
+PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct", "dense", "scan"]
 STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_TOL_NOT_REACHED",
           4: "THX_OUT_OF_MEMORY", 5: "THX_HIP_ERROR"}
 

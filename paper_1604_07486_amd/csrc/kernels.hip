@@ -623,6 +623,151 @@ void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s)
 }
 
 // ============================================================================
+// Unit steps (case 1): a parameter lowered by exactly 1 makes T and H constant,
+// so beta_j = D1_j t_0 h_0 sum_{k >= j, k - j in the kind's stride} D2_k alpha_k:
+// a suffix sum, computed as a reverse scan in FP64.  Each partial sum then
+// carries rounding relative to its own terms (an FFT's error is relative to
+// the largest term of the whole vector, which D1_j ~ j^(first+1) amplifies).
+// Parity kinds scan the even and odd indices together as the two components
+// of a lane (lane q = indices 2q, 2q+1); other kinds scan every index.
+// Pass 1: totals of chunks of SC_CH lanes; pass 2: reverse scan of each chunk
+// plus the sum of all later chunks (fixed order: deterministic).
+// ============================================================================
+constexpr int SC_NT = 256, SC_PER = 8, SC_CH = SC_NT * SC_PER;
+
+__device__ __forceinline__ void sc_lane(const KindDesc &k, const double *al, int64_t N, int64_t q, double &x,
+                                        double &y)
+{
+    x = y = 0.0;
+    if (k.parity) {
+        const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+        if (j0 <= N) x = d2_of(k, j0) * al[j0];
+        if (j1 <= N) y = d2_of(k, j1) * al[j1];
+    } else if (q <= N) {
+        x = d2_of(k, q) * al[q];
+    }
+}
+
+__device__ __forceinline__ void block_sum2(double &x, double &y, double *sx, double *sy)
+{
+    const int t = threadIdx.x;
+    sx[t] = x;
+    sy[t] = y;
+    __syncthreads();
+    for (int h = SC_NT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            sx[t] += sx[t + h];
+            sy[t] += sy[t + h];
+        }
+        __syncthreads();
+    }
+    x = sx[0];
+    y = sy[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                                      int64_t N0, double *tot, int nchunk)
+{
+    __shared__ double sx[SC_NT], sy[SC_NT];
+    const int c = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
+    const double *al = alpha + base;
+    double x = 0.0, y = 0.0;
+    const int64_t q0 = (int64_t)c * SC_CH + (int64_t)threadIdx.x * SC_PER;
+#pragma unroll
+    for (int i = SC_PER - 1; i >= 0; --i) {
+        double u, v;
+        sc_lane(k, al, N, q0 + i, u, v);
+        x += u;
+        y += v;
+    }
+    block_sum2(x, y, sx, sy);
+    if (threadIdx.x == 0) {
+        tot[2 * (b * nchunk + c)] = x;
+        tot[2 * (b * nchunk + c) + 1] = y;
+    }
+}
+
+__global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                                        double *beta, int64_t N0, const double *tot, int nchunk,
+                                                        const double *tsym, const double *hk)
+{
+    __shared__ double sx[SC_NT], sy[SC_NT];
+    const int c = blockIdx.x;
+    const int64_t b = blockIdx.y;
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
+    const int64_t nl = k.parity ? N / 2 + 1 : N + 1; // lanes of this vector
+    if ((int64_t)c * SC_CH >= nl) return;            // uniform over the block
+    const double *al = alpha + base;
+    // carry: everything after this chunk
+    double cx = 0.0, cy = 0.0;
+    for (int cc = c + 1 + (int)threadIdx.x; cc < nchunk; cc += SC_NT) {
+        cx += tot[2 * (b * nchunk + cc)];
+        cy += tot[2 * (b * nchunk + cc) + 1];
+    }
+    block_sum2(cx, cy, sx, sy);
+    // thread-local reverse inclusive scan of SC_PER lanes
+    const int64_t q0 = (int64_t)c * SC_CH + (int64_t)threadIdx.x * SC_PER;
+    double vx[SC_PER], vy[SC_PER];
+    double rx = 0.0, ry = 0.0;
+#pragma unroll
+    for (int i = SC_PER - 1; i >= 0; --i) {
+        double u, v;
+        sc_lane(k, al, N, q0 + i, u, v);
+        rx += u;
+        ry += v;
+        vx[i] = rx;
+        vy[i] = ry;
+    }
+    // exclusive reverse scan of the thread totals (Hillis-Steele over the block)
+    const int t = threadIdx.x;
+    sx[t] = rx;
+    sy[t] = ry;
+    __syncthreads();
+    for (int h = 1; h < SC_NT; h <<= 1) {
+        const double ax = t + h < SC_NT ? sx[t + h] : 0.0, ay = t + h < SC_NT ? sy[t + h] : 0.0;
+        __syncthreads();
+        sx[t] += ax;
+        sy[t] += ay;
+        __syncthreads();
+    }
+    const double ex = (t + 1 < SC_NT ? sx[t + 1] : 0.0) + cx, ey = (t + 1 < SC_NT ? sy[t + 1] : 0.0) + cy;
+    const double g = tsym[0] * hk[0];
+    double *be = beta + base;
+#pragma unroll
+    for (int i = 0; i < SC_PER; ++i) {
+        const int64_t q = q0 + i;
+        if (k.parity) {
+            const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+            if (j0 <= N) be[j0] = d1_of(k, j0) * g * (vx[i] + ex);
+            if (j1 <= N) be[j1] = d1_of(k, j1) * g * (vy[i] + ey);
+        } else if (q <= N) {
+            be[q] = d1_of(k, q) * g * (vx[i] + ex);
+        }
+    }
+}
+
+int suffix_chunks(const KindDesc &k, int64_t N)
+{
+    const int64_t nl = k.parity ? N / 2 + 1 : N + 1;
+    return (int)((nl + SC_CH - 1) / SC_CH);
+}
+
+void launch_suffix(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha, int64_t ld,
+                   double *beta, int64_t N, int64_t batch, const double *tsym, const double *hk, double *tot,
+                   hipStream_t s)
+{
+    const int nchunk = suffix_chunks(k, N);
+    dim3 grid((unsigned)nchunk, (unsigned)batch);
+    k_suffix_tot<<<grid, SC_NT, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tot, nchunk);
+    k_suffix_apply<<<grid, SC_NT, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, tot, nchunk, tsym, hk);
+}
+
+// ============================================================================
 // Dense path (short vectors): beta_b = A alpha_b as one batched product
 // ============================================================================
 // The matrix is an O(N^2) object anyway below the FFT crossover; materialised

@@ -119,6 +119,13 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s);
 // I[k][k] = 1 for k < n (row stride ld; the rest must already be zero)
 void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s);
 
+// ---- unit steps: beta = D1 t_0 h_0 (suffix sums of D2 alpha) ----------------------
+// tot: [batch][suffix_chunks][2] doubles of workspace
+int suffix_chunks(const KindDesc &k, int64_t N);
+void launch_suffix(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha, int64_t ld,
+                   double *beta, int64_t N, int64_t batch, const double *tsym, const double *hk, double *tot,
+                   hipStream_t s);
+
 // ---- dense path: beta_b = A alpha_b with A materialised ----------------------------
 // At[k][j] = A[j][k], row-major with stride npad (a multiple of DENSE_PAD), zero
 // outside 0..N and for k < j (A upper triangular).  off / deg as for pack.

@@ -124,8 +124,9 @@ struct thx_plan {
     bool is_jac_stage = false;
     bool row0_direct = false; // row 0 by a direct dot product (Hankel PSD on indices >= 1 only)
     JacStage jac;
-    thx_plan *next = nullptr; // second stage of a two-stage conversion
-    double *tmp = nullptr;    // intermediate coefficients between the stages
+    thx_plan *next = nullptr; // next stage of a multi-stage conversion
+    double *tmp = nullptr;    // intermediate coefficients between stages (ping-pong pair
+    double *tmp2 = nullptr;   // for chains of three or more), owned by the first stage
     int64_t tmp_elems = 0;
     double params[4] = {0, 0, 0, 0};
     int64_t N = 0;
@@ -133,7 +134,7 @@ struct thx_plan {
     thx_precision prec = THX_FP64;
     uint32_t flags = 0;
     KindDesc kd{};
-    int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense
+    int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense, 4 unit step (suffix sums)
     double *dense = nullptr; // path 3 (reported): At[k][j] = A[j][k], stride dense_ld; the
     int64_t dense_ld = 0;    // stages keep their own path for re-tuning
     // launch shapes (workgroups targeted per launch), set by the autotuner
@@ -168,6 +169,7 @@ struct thx_plan {
     void *X = nullptr, *Wp = nullptr, *U = nullptr;
     double *row0 = nullptr;
     double *row0_part = nullptr; // [batch][ROW0_PMAX] partial sums of row 0
+    double *sfx_tot = nullptr;   // path 4: [batch][chunks][2] chunk totals
     int64_t U_slots = 0;
     int Gmax = 0;
     // per-phase event timing
@@ -206,10 +208,12 @@ struct thx_plan {
         dfree(U);
         dfree(row0);
         dfree(row0_part);
+        dfree(sfx_tot);
         delete[] pivots[0];
         delete[] pivots[1];
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         dfree(tmp);
+        dfree(tmp2);
         dfree(dense);
         delete next;
     }
@@ -474,9 +478,9 @@ thx_status validate_kind(thx_kind kind, const double *params, int nparams, doubl
         const double dl = l1 - l2;
         out[0] = l1;
         out[1] = l2;
-        // Hankel part PSD needs l1 - l2 <= 1 (Sec. 5.2, case 2); integer differences
-        // other than 0 and 1 are the banded case 1
-        if (dl > 1.0) return THX_UNSUPPORTED;
+        // one stage: l1 - l2 <= 1 (case 2; negative integer differences are the
+        // banded case 1); larger differences are chained unit steps (case 3)
+        (void)dl;
         return THX_OK;
     }
     case THX_JAC2JAC:
@@ -505,6 +509,28 @@ thx_status validate_kind(thx_kind kind, const double *params, int nparams, doubl
 thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const JacStage *jac, int64_t degree,
                          double tol, thx_precision prec, uint32_t flags, hipStream_t s);
 
+// Link `n` stages made by make(i, &plan) into one plan (the first stage owns the rest).
+template <typename Make>
+thx_status create_chain(thx_plan **out, size_t n, Make &&make)
+{
+    thx_plan *first = nullptr, *last = nullptr;
+    thx_status r = THX_OK;
+    for (size_t i = 0; i < n; ++i) {
+        thx_plan *q = nullptr;
+        const thx_status ri = make(i, &q);
+        if (ri != THX_OK && ri != THX_TOL_NOT_REACHED) {
+            delete first;
+            return ri;
+        }
+        if (ri == THX_TOL_NOT_REACHED) r = ri;
+        if (last) last->next = q;
+        else first = q;
+        last = q;
+    }
+    *out = first;
+    return r;
+}
+
 // Jacobi conversions (Sec. 5.3): a change of the second parameter b -> d first
 // (reflected stage), then of the first a -> g; each stage must be case 2
 // (|a - g| < 1 or a - g = 1, and a + b > -1 so that the Hankel part is PSD).
@@ -522,34 +548,52 @@ thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_
         a = -0.5, b = -0.5, g = pv[0], d = pv[1];
         cheb_first = 2;
     }
+    // Sec. 5.3, case 4: while the first parameter must move by more than 1 (and
+    // not by a whole number upwards, which is one banded case-1 stage), move it
+    // by exactly 1 towards the target: down, T and H are constant (unit step,
+    // suffix sums); up, T is bidiagonal (banded).  The last stage moves it by at
+    // most 1 (case 2 or 3).  (A single case-2 stage over a larger rise is PSD
+    // but its diagonal scalings amplify rounding: measured 4e-9 for a rise of 3.)
     std::vector<JacStage> st;
-    if (b != d) st.push_back(JacStage{b, a, d, 1, 0}); // (b, a) -> (d, a), reflected
-    if (a != g || st.empty()) st.push_back(JacStage{a, d, g, 0, 0});
+    auto steps = [&](double x, double y, double other, int reflect) {
+        while (std::fabs(x - y) > 1.0 && !(y > x && neg_integer(x - y))) {
+            const double nx = x > y ? x - 1.0 : x + 1.0;
+            st.push_back(JacStage{x, other, nx, reflect, 0});
+            x = nx;
+        }
+        st.push_back(JacStage{x, other, y, reflect, 0});
+    };
+    if (b != d) steps(b, d, a, 1); // (b, a) -> (d, a), reflected
+    if (a != g || st.empty()) steps(a, g, d, 0);
     st.front().cheb = cheb_first ? cheb_first : st.front().cheb;
     if (cheb_last) {
         if (cheb_first == 0 && st.size() == 1 && st[0].cheb == 0) st[0].cheb = 1;
         else st.back().cheb = 1;
     }
-    for (const JacStage &J : st) {
-        // case 3 (a + b <= -1) runs with row 0 computed directly, case 1 (integer
-        // steps down) with the banded Toeplitz factor; case 4 (first parameter
-        // moving by more than 1) is not built
-        if (J.a - J.g > 1.0) return THX_UNSUPPORTED;
+    // case 3 (a + b <= -1) runs with row 0 computed directly, case 1 (integer
+    // steps up) with the banded Toeplitz factor
+    return create_chain(out, st.size(), [&](size_t i, thx_plan **o) {
+        return create_single(o, kind, pv, &st[i], degree, tol, prec, flags, s);
+    });
+}
+
+// ultraspherical, Sec. 5.2 case 3: |lambda1 - lambda2| > 1 (not a whole-number
+// rise) moves lambda1 in unit steps towards lambda2, then the remainder (<= 1)
+thx_status create_ultra(thx_plan **out, const double *pv, int64_t degree, double tol, thx_precision prec,
+                        uint32_t flags, hipStream_t s)
+{
+    std::vector<std::pair<double, double>> st;
+    double l = pv[0];
+    while (std::fabs(l - pv[1]) > 1.0 && !(pv[1] > l && neg_integer(l - pv[1]))) {
+        const double nl = l > pv[1] ? l - 1.0 : l + 1.0;
+        st.push_back({l, nl});
+        l = nl;
     }
-    thx_plan *first = nullptr, *second = nullptr;
-    thx_status r = create_single(&first, kind, pv, &st[0], degree, tol, prec, flags, s);
-    if (r != THX_OK && r != THX_TOL_NOT_REACHED) return r;
-    if (st.size() > 1) {
-        thx_status r2 = create_single(&second, kind, pv, &st[1], degree, tol, prec, flags, s);
-        if (r2 != THX_OK && r2 != THX_TOL_NOT_REACHED) {
-            delete first;
-            return r2;
-        }
-        if (r2 == THX_TOL_NOT_REACHED) r = r2;
-        first->next = second;
-    }
-    *out = first;
-    return r;
+    st.push_back({l, pv[1]});
+    return create_chain(out, st.size(), [&](size_t i, thx_plan **o) {
+        const double q[4] = {st[i].first, st[i].second, 0.0, 0.0};
+        return create_single(o, THX_ULTRA2ULTRA, q, nullptr, degree, tol, prec, flags, s);
+    });
 }
 
 void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
@@ -587,8 +631,9 @@ void build_dense(thx_plan *p, hipStream_t s)
         throw;
     }
     dfree(I);
-    dfree(p->tmp); // the stages' intermediate is not used by the dense product
-    p->tmp = nullptr;
+    dfree(p->tmp); // the stages' intermediates are not used by the dense product
+    dfree(p->tmp2);
+    p->tmp = p->tmp2 = nullptr;
     p->tmp_elems = 0;
     p->dense = At;
     p->dense_ld = npad;
@@ -604,9 +649,13 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
     double pv[4] = {0, 0, 0, 0};
     thx_status vs = validate_kind(kind, params, nparams, pv);
     if (vs != THX_OK) return vs;
-    thx_status r = (kind == THX_JAC2JAC || kind == THX_JAC2CHEB || kind == THX_CHEB2JAC)
-                       ? create_jacobi(out, kind, pv, degree, tol, prec, flags, s)
-                       : create_single(out, kind, pv, nullptr, degree, tol, prec, flags, s);
+    thx_status r;
+    if (kind == THX_JAC2JAC || kind == THX_JAC2CHEB || kind == THX_CHEB2JAC)
+        r = create_jacobi(out, kind, pv, degree, tol, prec, flags, s);
+    else if (kind == THX_ULTRA2ULTRA && std::fabs(pv[0] - pv[1]) > 1.0)
+        r = create_ultra(out, pv, degree, tol, prec, flags, s);
+    else
+        r = create_single(out, kind, pv, nullptr, degree, tol, prec, flags, s);
     if ((r != THX_OK && r != THX_TOL_NOT_REACHED) || !dense_eligible(*out, flags)) return r;
     try {
         build_dense(*out, s);
@@ -663,8 +712,15 @@ thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const 
         const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
                             (!(flags & THX_FLAG_FORCE_FFT) && degree <= direct_crossover()) ||
                             degree < 2 || p->kd.band >= 0;
+        // a parameter lowered by exactly 1: T and H constant (case 1 by suffix sums)
+        const bool unit = !p->row0_direct && p->kd.band < 0 &&
+                          ((jac && jac->a - jac->g == 1.0) ||
+                           ((kind == THX_ULTRA2ULTRA || kind == THX_LAG2LAG) && pv[0] - pv[1] == 1.0));
         if (direct) {
             p->path = 0;
+            hip_check(hipStreamSynchronize(s));
+        } else if (unit) {
+            p->path = 4;
             hip_check(hipStreamSynchronize(s));
         } else {
             build_fft(p, s);
@@ -716,6 +772,14 @@ struct PhaseTimer {
 void ensure_workspace(thx_plan *p, int64_t batch)
 {
     if (batch <= p->ws_batch) return;
+    if (p->path == 4) {
+        dfree(p->sfx_tot);
+        p->sfx_tot = nullptr;
+        p->ws_batch = 0;
+        p->sfx_tot = dalloc<double>(2 * batch * suffix_chunks(p->kd, p->N));
+        p->ws_batch = batch;
+        return;
+    }
     dfree(p->X);
     dfree(p->Wp);
     dfree(p->U);
@@ -814,9 +878,11 @@ void ensure_tmp(thx_plan *p, int64_t elems)
 {
     if (elems <= p->tmp_elems) return;
     dfree(p->tmp);
-    p->tmp = nullptr;
+    dfree(p->tmp2);
+    p->tmp = p->tmp2 = nullptr;
     p->tmp_elems = 0;
     p->tmp = dalloc<double>(elems);
+    if (p->next && p->next->next) p->tmp2 = dalloc<double>(elems);
     p->tmp_elems = elems;
 }
 
@@ -838,13 +904,26 @@ void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const dou
         return;
     }
     ensure_tmp(p, tmp_elems);
-    execute_stage(p, off, deg, alpha, p->tmp, degree, batch, ld, s);
-    execute_stage(p->next, off, deg, p->tmp, beta, degree, batch, ld, s);
+    double *bufs[2] = {p->tmp, p->tmp2};
+    const double *in = alpha;
+    int k = 0;
+    for (thx_plan *q = p; q; q = q->next) {
+        double *out = q->next ? bufs[(k++) & 1] : beta;
+        execute_stage(q, off, deg, in, out, degree, batch, ld, s);
+        in = out;
+    }
 }
 
 void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
                    int64_t degree, int64_t batch, int64_t ld, hipStream_t s)
 {
+    if (p->path == 4 && degree >= 2) {
+        ensure_workspace(p, batch);
+        PhaseTimer t(p, THX_PHASE_SCAN, s);
+        launch_suffix(p->kd, off, deg, alpha, ld, beta, degree, batch, p->tsym, p->hk, p->sfx_tot, s);
+        launch_check();
+        return;
+    }
     if (p->path == 0 || degree < 2) {
         PhaseTimer t(p, THX_PHASE_DIRECT, s);
         launch_direct(p->kd, off, deg, alpha, ld, beta, degree, batch, p->tsym, p->hk, s);
@@ -1284,7 +1363,7 @@ thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols
 }
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {
-    if (!p || part < 0 || part >= p->parts || p->path == 0) return -1.0;
+    if (!p || part < 0 || part >= p->parts || p->path == 0 || p->path == 4) return -1.0;
     return p->dfinal[part];
 }
 

@@ -258,10 +258,39 @@ def test_cheb2leg_fft_fp32(thx, N):
 
 
 @pytest.mark.parametrize("l1,l2,N", [(1.5, 0.5, 255), (1.5, 0.5, 3000), (0.75, 0.25, 1500), (1.0, 0.5, 9000),
-                                     (0.5, 1.25, 2000), (0.3, 0.3, 50), (0.5, 2.5, 4000)])
+                                     (0.5, 1.25, 2000), (0.3, 0.3, 50), (0.5, 2.5, 4000), (0.25, 2.0, 3000),
+                                     # Sec. 5.2 case 3: unit steps down, then the remainder
+                                     (3.5, 0.5, 3000), (3.25, 0.5, 2500), (4.75, 1.0, 900), (2.0, 0.5, 5000)])
 def test_ultra2ultra(thx, l1, l2, N):
     _check_full(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(l1, l2), flags=thx.FLAG_FORCE_FFT, seed=N,
                 scale_bar=True)
+
+
+# unit steps (a parameter lowered by exactly 1): T and H constant, suffix sums (path 4)
+@pytest.mark.parametrize("kind,params,N,prec", [(2, (1.5, 0.5), 20000, 0), (2, (4.25, 3.25), 9000, 0),
+                                                (2, (1.5, 0.5), 20001, 1), (4, (1.5, 0.5), 6000, 0),
+                                                (4, (0.25, -0.75), 3000, 0)])
+def test_unit_step_suffix_sum(thx, kind, params, N, prec):
+    plan, _ = _check_full(thx, kind, N, prec, params=params, flags=thx.FLAG_FORCE_FFT, seed=N,
+                          scale_bar=(kind == 2))
+    assert plan.path == 4
+
+
+def test_unit_step_full_size_sampled(thx):
+    N = 1 << 20
+    plan, alpha, got = _run(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(1.5, 0.5), seed=5)
+    assert plan.path == 4
+    rows = inputs.sample_rows(N, 128, seed=3)
+    ref = oracle.matvec("ultra2ultra", alpha, (1.5, 0.5), rows=rows)
+    err = float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+    print(f"  sampled err={err:.3e}", flush=True)
+    assert err < TOL64 * (2 * N + 1)
+
+
+@pytest.mark.parametrize("l1,l2,N,prec", [(3.5, 0.5, 300, 0), (3.25, 0.5, 255, 1), (5.5, 0.75, 120, 0)])
+def test_ultra2ultra_chain_dense(thx, l1, l2, N, prec):
+    plan, _ = _check_full(thx, thx.ULTRA2ULTRA, N, prec, params=(l1, l2), seed=N, bar=TOL64, scale_bar=True)
+    assert plan.path == 3
 
 
 @pytest.mark.parametrize("a1,a2,N", [(0.5, -0.25, 700), (1.25, 0.5, 3000), (-0.5, 1.5, 2000)])
@@ -512,6 +541,14 @@ def _jac_scale(kind, N, params):
     (3, (-0.5, -0.75, -0.25, -0.75), 300, 0, 0),
     (3, (-0.5, 0.3, 1.5, 0.3), 200, 0, 0),
     (5, (0.5, -0.25), 255, 0, 4),                              # entry by entry
+    # case 4: a parameter dropping by more than 1 goes down in unit steps
+    (3, (2.5, 0.0, 0.0, 0.0), 1000, 0, 2),
+    (5, (1.9, -0.5), 1500, 0, 2),
+    (5, (1.9, -0.5), 255, 0, 0),
+    (3, (0.2, 2.7, 0.2, 0.1), 800, 0, 2),                       # reflected steps
+    (3, (0.2, 2.7, 0.2, 0.1), 200, 1, 0),
+    (6, (2.6, 1.3), 700, 0, 2),                                # Chebyshev to Jacobi: rises
+    (3, (1.5, 0.25, 0.5, 0.25), 7000, 0, 2),                   # one unit step (suffix sums)
 ])
 def test_jacobi(thx, kind, params, N, prec, flags):
     import torch
