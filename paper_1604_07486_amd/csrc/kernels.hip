@@ -666,6 +666,9 @@ __device__ __forceinline__ void block_sum2(double &x, double &y, double *sx, dou
     __syncthreads();
 }
 
+// Global memory is read and written with consecutive lanes on consecutive
+// threads; the chunk goes through LDS so that each thread can scan a run of
+// SC_PER consecutive lanes.
 __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
                                                       int64_t N0, double *tot, int nchunk)
 {
@@ -676,11 +679,10 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, con
     vec_of(vr, b, ld, N0, base, N);
     const double *al = alpha + base;
     double x = 0.0, y = 0.0;
-    const int64_t q0 = (int64_t)c * SC_CH + (int64_t)threadIdx.x * SC_PER;
 #pragma unroll
-    for (int i = SC_PER - 1; i >= 0; --i) {
+    for (int i = 0; i < SC_PER; ++i) {
         double u, v;
-        sc_lane(k, al, N, q0 + i, u, v);
+        sc_lane(k, al, N, (int64_t)c * SC_CH + threadIdx.x + SC_NT * i, u, v);
         x += u;
         y += v;
     }
@@ -691,10 +693,16 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, con
     }
 }
 
+// LDS index of chunk lane i, padded one slot per 32 against bank conflicts of
+// the per-thread runs
+__device__ __forceinline__ int sc_pad(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
                                                         double *beta, int64_t N0, const double *tot, int nchunk,
                                                         const double *tsym, const double *hk)
 {
+    constexpr int LP = SC_CH + SC_CH / 32;
+    __shared__ double lx[LP], ly[LP];
     __shared__ double sx[SC_NT], sy[SC_NT];
     const int c = blockIdx.x;
     const int64_t b = blockIdx.y;
@@ -703,28 +711,33 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
     const int64_t nl = k.parity ? N / 2 + 1 : N + 1; // lanes of this vector
     if ((int64_t)c * SC_CH >= nl) return;            // uniform over the block
     const double *al = alpha + base;
+    const int t = threadIdx.x;
+    const int64_t q0 = (int64_t)c * SC_CH;
+#pragma unroll
+    for (int i = 0; i < SC_PER; ++i) {
+        double u, v;
+        sc_lane(k, al, N, q0 + t + SC_NT * i, u, v);
+        lx[sc_pad(t + SC_NT * i)] = u;
+        ly[sc_pad(t + SC_NT * i)] = v;
+    }
     // carry: everything after this chunk
     double cx = 0.0, cy = 0.0;
-    for (int cc = c + 1 + (int)threadIdx.x; cc < nchunk; cc += SC_NT) {
+    for (int cc = c + 1 + t; cc < nchunk; cc += SC_NT) {
         cx += tot[2 * (b * nchunk + cc)];
         cy += tot[2 * (b * nchunk + cc) + 1];
     }
-    block_sum2(cx, cy, sx, sy);
-    // thread-local reverse inclusive scan of SC_PER lanes
-    const int64_t q0 = (int64_t)c * SC_CH + (int64_t)threadIdx.x * SC_PER;
+    block_sum2(cx, cy, sx, sy); // also orders the LDS stores above before the reads below
+    // reverse inclusive scan of this thread's run of SC_PER lanes
     double vx[SC_PER], vy[SC_PER];
     double rx = 0.0, ry = 0.0;
 #pragma unroll
     for (int i = SC_PER - 1; i >= 0; --i) {
-        double u, v;
-        sc_lane(k, al, N, q0 + i, u, v);
-        rx += u;
-        ry += v;
+        rx += lx[sc_pad(t * SC_PER + i)];
+        ry += ly[sc_pad(t * SC_PER + i)];
         vx[i] = rx;
         vy[i] = ry;
     }
-    // exclusive reverse scan of the thread totals (Hillis-Steele over the block)
-    const int t = threadIdx.x;
+    // exclusive reverse scan of the run totals (Hillis-Steele over the block)
     sx[t] = rx;
     sy[t] = ry;
     __syncthreads();
@@ -736,17 +749,24 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
         __syncthreads();
     }
     const double ex = (t + 1 < SC_NT ? sx[t + 1] : 0.0) + cx, ey = (t + 1 < SC_NT ? sy[t + 1] : 0.0) + cy;
+#pragma unroll
+    for (int i = 0; i < SC_PER; ++i) {
+        lx[sc_pad(t * SC_PER + i)] = vx[i] + ex;
+        ly[sc_pad(t * SC_PER + i)] = vy[i] + ey;
+    }
+    __syncthreads();
     const double g = tsym[0] * hk[0];
     double *be = beta + base;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
-        const int64_t q = q0 + i;
+        const int li = t + SC_NT * i;
+        const int64_t q = q0 + li;
         if (k.parity) {
             const int64_t j0 = 2 * q, j1 = 2 * q + 1;
-            if (j0 <= N) be[j0] = d1_of(k, j0) * g * (vx[i] + ex);
-            if (j1 <= N) be[j1] = d1_of(k, j1) * g * (vy[i] + ey);
+            if (j0 <= N) be[j0] = d1_of(k, j0) * g * lx[sc_pad(li)];
+            if (j1 <= N) be[j1] = d1_of(k, j1) * g * ly[sc_pad(li)];
         } else if (q <= N) {
-            be[q] = d1_of(k, q) * g * (vx[i] + ex);
+            be[q] = d1_of(k, q) * g * lx[sc_pad(li)];
         }
     }
 }
