@@ -363,13 +363,8 @@ def main():
     dom = max(tim.items(), key=lambda kv: kv[1][0])
     dname, (dtot, dcount) = dom
     davg_ms = dtot / dcount
-    # partial-sum groups of the inverse column pass (the library's rule:
-    # about 1024 workgroups over the column tiles)
-    L1, L2, TC = plan.fft_geometry()
-    tiles = L1 // TC
-    Gc = min(S, max(1, -(-1024 // tiles)))
-    spg = -(-S // Gc)
-    Gc = -(-S // spg)
+    # partial-sum groups of the inverse column pass, as the tuned plan runs it
+    Gc = plan.partial_groups(1)
     dbytes = phase_bytes(dname, es, S, nc, L, Gc)
     roof = None
     if dbytes is not None:
@@ -448,6 +443,8 @@ def main():
         "plan_ms": round(plan_ms, 2),
         "autotune_ms": round(tune_ms, 2),
         "fft_geometry": list(plan.fft_geometry()) if plan.path == 2 else None,
+        "launch_shape": {"lds_blocks": plan.launch_shape()[0], "p3_blocks": plan.launch_shape()[1],
+                         "partial_groups": Gc},
         "copy_gbs_measured": round(copy_gbs, 1),
         "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
         "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim.items()},

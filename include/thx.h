@@ -129,6 +129,14 @@ int32_t thx_plan_path(const thx_plan *plan);
  * any output pointer may be NULL. */
 thx_status thx_plan_fft_geometry(const thx_plan *plan, int64_t *rows, int64_t *cols,
                                  int64_t *tile_cols);
+/* Launch shapes of the (first) stage, as set by thx_plan_autotune (defaults 512
+ * and 1024): workgroups targeted per launch of the single-workgroup path and of
+ * the inverse column pass.  Any output pointer may be NULL;
+ * THX_INVALID_ARGUMENT for a null plan. */
+thx_status thx_plan_launch_shape(const thx_plan *plan, int32_t *lds_blocks, int32_t *p3_blocks);
+/* Partial-sum groups the (first) stage uses for an execution of `batch` vectors
+ * (the extra reads of the final D1 step); 0 for paths without them. */
+int32_t thx_plan_partial_groups(const thx_plan *plan, int64_t batch);
 /* Tune a plan for executions of `batch` vectors of its degree (the launch
  * shapes, row length and crossover that Sec. 2.1's reuse of one plan makes
  * worth choosing once): every FFT stage times its candidate launch shapes

@@ -47,6 +47,8 @@ _sig("thx_plan_fft_length", _i64, _vp)
 _sig("thx_plan_path", _i32, _vp)
 _sig("thx_plan_fft_geometry", ctypes.c_int, _vp, _p64, _p64, _p64)
 _sig("thx_plan_autotune", ctypes.c_int, _vp, _i64, _vp)
+_sig("thx_plan_launch_shape", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+_sig("thx_plan_partial_groups", _i32, _vp, _i64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
      ctypes.POINTER(_i64), _vp)
@@ -131,6 +133,15 @@ class Plan:
         """Choose launch shapes / dense vs FFT for executions of `batch` vectors."""
         _check(_lib.thx_plan_autotune(self._h, int(batch), _stream(stream)), "thx_plan_autotune")
         return self
+
+    def launch_shape(self):
+        """(lds_blocks, p3_blocks): workgroups targeted per launch (set by autotune)."""
+        a, c = _i32(), _i32()
+        _check(_lib.thx_plan_launch_shape(self._h, ctypes.byref(a), ctypes.byref(c)), "thx_plan_launch_shape")
+        return a.value, c.value
+
+    def partial_groups(self, batch: int = 1) -> int:
+        return int(_lib.thx_plan_partial_groups(self._h, int(batch)))
 
     def fft_geometry(self):
         """(rows, cols, tile_cols) of the three-pass FFT (path 2 only)."""

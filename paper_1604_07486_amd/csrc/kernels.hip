@@ -1245,14 +1245,30 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
             F::out_pos(e, k2, c);
             v[e] = ld_stream(Ub + a1_0 + c + (int64_t)L1 * k2);
         }
-        F::inverse(v, lds, twL2);
         const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
+        if constexpr (sizeof(T) == 4) {
+            // l~_s read with the tile: one memory round trip per slot (in double
+            // precision the extra registers spill, and it measured slower)
+            cpx<T> el[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            int a2, c;
-            F::in_pos(e, a2, c);
-            const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-            if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], v[e]));
+            for (int e = 0; e < E; ++e) {
+                int a2, c;
+                F::in_pos(e, a2, c);
+                const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+                el[e] = a < n ? es[a] : cpx<T>{0, 0};
+            }
+            F::inverse(v, lds, twL2);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cdiag(el[e], v[e]));
+        } else {
+            F::inverse(v, lds, twL2);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                int a2, c;
+                F::in_pos(e, a2, c);
+                const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+                if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], v[e]));
+            }
         }
     }
     cpx<T> *Wg = W + ((int64_t)(gofs + g) * batch + b) * nc;

@@ -1353,6 +1353,34 @@ int64_t thx_plan_fft_length(const thx_plan *p)
     return L;
 }
 int32_t thx_plan_path(const thx_plan *p) { return p ? (p->dense ? 3 : p->path) : -1; }
+thx_status thx_plan_launch_shape(const thx_plan *p, int32_t *lds_blocks, int32_t *p3_blocks)
+{
+    if (!p) return THX_INVALID_ARGUMENT;
+    if (lds_blocks) *lds_blocks = p->lds_blocks;
+    if (p3_blocks) *p3_blocks = p->p3_blocks;
+    return THX_OK;
+}
+
+int32_t thx_plan_partial_groups(const thx_plan *p, int64_t batch)
+{
+    if (!p || batch < 1 || p->dense || p->S <= 0) return 0;
+    if (p->path == 1) {
+        const int64_t Gt = std::min<int64_t>(p->S, std::max<int64_t>(1, (p->lds_blocks + batch - 1) / batch));
+        const int64_t spg = (p->S + Gt - 1) / Gt;
+        return (int32_t)((p->S + spg - 1) / spg);
+    }
+    if (p->path != 2) return 0;
+    const int64_t tiles = p->geom.L1 / p->geom.TC;
+    int64_t G = 0;
+    for (int64_t s0 = 0; s0 < p->S; s0 += std::max<int64_t>(1, p->U_slots ? p->U_slots : p->S)) {
+        const int64_t ns = std::min<int64_t>(p->U_slots ? p->U_slots : p->S, p->S - s0);
+        int64_t Gc = std::min<int64_t>(ns, std::max<int64_t>(1, (p->p3_blocks + tiles * batch - 1) / (tiles * batch)));
+        const int64_t spg = (ns + Gc - 1) / Gc;
+        G += (ns + spg - 1) / spg;
+    }
+    return (int32_t)G;
+}
+
 thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols, int64_t *tile_cols)
 {
     if (!p || p->path != 2 || p->dense) return THX_INVALID_ARGUMENT;

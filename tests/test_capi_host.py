@@ -108,6 +108,12 @@ def test_introspection_null_plan(lib):
     lib.thx_plan_fft_geometry.restype = ctypes.c_int
     lib.thx_plan_fft_geometry.argtypes = [ctypes.c_void_p] * 4
     assert lib.thx_plan_fft_geometry(None, None, None, None) == 1
+    lib.thx_plan_launch_shape.restype = ctypes.c_int
+    lib.thx_plan_launch_shape.argtypes = [ctypes.c_void_p] * 3
+    assert lib.thx_plan_launch_shape(None, None, None) == 1
+    lib.thx_plan_partial_groups.restype = ctypes.c_int32
+    lib.thx_plan_partial_groups.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    assert lib.thx_plan_partial_groups(None, 1) == 0
 
 
 def test_table_rejects_negative_count(lib):
