@@ -361,6 +361,42 @@ def test_batch_graph_replays_match_eager(thx):
         (junk * 2.0).sum().item()
 
 
+@pytest.mark.parametrize("kind,params", [(2, (1.5, 0.5)), (5, (0.5, -0.25)), (2, (3.25, 0.5))])
+def test_batch_config5_kinds(thx, kind, params):
+    """Many short vectors (dense bucket) plus a few long ones (FFT or unit-step buckets) in one CSR
+    batch, as in the config-5 workload at reduced size; eager and graph replays."""
+    import torch
+    degrees = np.array([255] * 700 + [40, 3] + [20000, 30001], dtype=np.int64)
+    print(f"[case] batch kind={kind} params={params} members={len(degrees)}", flush=True)
+    flat, parts = _batch_inputs(degrees, 1.0, 17)
+    bt = thx.Batch(kind, degrees, EPS64, thx.FP64, params=params)
+    print(f"  buckets={bt.buckets()}", flush=True)
+    a = _dev(flat)
+    out = torch.full_like(a, float("nan"))
+    bt.execute(a, out)
+    graph = torch.full_like(a, float("nan"))
+    bt.execute(a, graph, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, graph)
+    got = out.cpu().numpy()
+    for i in [0, 350, 699, 700, 701, 702, 703]:
+        al = parts[i]
+        o = int(bt.offsets[i])
+        n = len(al) - 1
+        if kind == 2:
+            rows = None if n <= 4096 else inputs.sample_rows(n, 48, seed=i)
+            ref = oracle.matvec("ultra2ultra", al, params, rows=rows)
+            g = got[o:o + n + 1] if rows is None else got[o:o + n + 1][rows]
+            bar = TOL64 * max(1.0, oracle.absmax("ultra2ultra", min(n, 400), params) * (n / min(n, 400)) ** 3)
+        else:
+            if n > 4096:
+                continue                      # the 2^18-class members are covered elsewhere
+            ref, g = _jac_ref(kind, al, params), got[o:o + n + 1]
+            bar = TOL64 * _jac_scale(kind, n, params)
+        err = float(np.max(np.abs(g - ref)) / np.sum(np.abs(al)))
+        assert err < bar, (i, n, err, bar)
+
+
 def test_batch_empty_and_bad_degree(thx):
     bt = thx.Batch(thx.LEG2CHEB, np.zeros(0, dtype=np.int64), EPS64)
     assert bt.coefficients == 0
