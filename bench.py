@@ -176,12 +176,17 @@ def phase_bytes(phase, es, S, nc, L, G, batch=1):
     return None
 
 
-def time_plan(thx, torch, plan, a, b, steps, warmup):
+def time_plan(thx, torch, plan, a, b, steps, warmup, phase=None):
+    """Milliseconds per execution over `steps` timed executions.  With `phase`,
+    that phase's launches are bracketed by HIP events inside the timed loop (two
+    events per launch: the other phases run without markers, which would add a
+    few microseconds each)."""
     for _ in range(warmup):
         plan.execute(a, b)
     torch.cuda.synchronize()
     plan.timings(reset=True)
-    plan.enable_timing(True)
+    if phase is not None:
+        plan.enable_timing(True, phases=(phase,))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -190,6 +195,23 @@ def time_plan(thx, torch, plan, a, b, steps, warmup):
     t1 = time.perf_counter()
     plan.enable_timing(False)
     return (t1 - t0) * 1e3 / steps, plan.timings(reset=True)
+
+
+def phase_breakdown(torch, plan, a, b, steps):
+    """{phase: (total_ms, launches)} from executions with every phase timed; run
+    outside the timed loop, since the markers slow the step down."""
+    torch.cuda.synchronize()
+    plan.timings(reset=True)
+    plan.enable_timing(True)
+    for _ in range(steps):
+        plan.execute(a, b)
+    torch.cuda.synchronize()
+    plan.enable_timing(False)
+    return plan.timings(reset=True)
+
+
+def phase_avg(tim):
+    return {k: round(v[0] / v[1], 5) for k, v in tim.items()}
 
 
 def sampled_error(oracle, kind, alpha, got, rows):
@@ -321,11 +343,12 @@ def main():
         prec = thx.FP64 if args.prec == "fp64" else thx.FP32_BULK
         plan = thx.Plan(thx.LEG2CHEB, N, 1e-15 if prec == thx.FP64 else 1e-7, prec)
         plan.autotune(1)
-        ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
+        ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase="row")
+        parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
         print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
-                          "K": plan.rank, "L": plan.fft_length,
-                          "phases_ms_avg": {k: v[0] / v[1] for k, v in tim.items()}}), flush=True)
+                          "K": plan.rank, "L": plan.fft_length, "row_ms_avg": phase_avg(tim).get("row"),
+                          "phases_ms_avg": phase_avg(parts)}), flush=True)
         return
 
     import oracle
@@ -351,7 +374,12 @@ def main():
     torch.cuda.synchronize()
     tune_ms = (time.perf_counter() - t0) * 1e3
 
-    ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup)
+    # per-phase split first (untimed for the value), to name the dominant kernel
+    for _ in range(args.warmup):
+        plan.execute(a, b)
+    parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
+    dname = max(parts.items(), key=lambda kv: kv[1][0])[0]
+    ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase=dname)
     value = (N + 1) / (ms * 1e-3)
     rows = inputs.sample_rows(N, 256, seed=17)
     err64 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
@@ -360,8 +388,7 @@ def main():
     S, L = plan.rank, plan.fft_length
     nc = N // 2 + 1
     es = 16
-    dom = max(tim.items(), key=lambda kv: kv[1][0])
-    dname, (dtot, dcount) = dom
+    dtot, dcount = tim[dname]
     davg_ms = dtot / dcount
     # partial-sum groups of the inverse column pass, as the tuned plan runs it
     Gc = plan.partial_groups(1)
@@ -381,7 +408,8 @@ def main():
     # ---- FP32-bulk at the same N (Lambda, Cholesky, D1/D2 in FP64) ----
     plan32 = thx.Plan(thx.LEG2CHEB, N, 1e-7, thx.FP32_BULK)
     plan32.autotune(1)
-    ms32, tim32 = time_plan(thx, torch, plan32, a, b, args.steps, args.warmup)
+    ms32, _ = time_plan(thx, torch, plan32, a, b, args.steps, args.warmup)
+    tim32 = phase_breakdown(torch, plan32, a, b, max(5, args.steps // 5))
     err32 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
     K32 = plan32.rank
     del plan32
@@ -447,10 +475,10 @@ def main():
                          "partial_groups": Gc},
         "copy_gbs_measured": round(copy_gbs, 1),
         "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
-        "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim.items()},
+        "phases_ms_avg": phase_avg(parts),
         "fp32_bulk": {"coeffs_per_s": round((N + 1) / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 5),
                       "K": K32, "max_err_over_l1": err32, "bar": 5e-6, "hankel_tol": 1e-7,
-                      "phases_ms_avg": {k: round(v[0] / v[1], 5) for k, v in tim32.items()}},
+                      "phases_ms_avg": phase_avg(tim32)},
         "batched": batch_res,
         "config5": conf5,
         "cheb2leg_fp64": {"coeffs_per_s": round((N + 1) / (msc * 1e-3), 1), "ms_per_step": round(msc, 5),

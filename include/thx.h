@@ -221,9 +221,12 @@ thx_status thx_lambda_table(double *out, int64_t count, double z0, hipStream_t s
 thx_status thx_gamma_ratio_table(double *out, int64_t count, double z0, double a, double b,
                                  hipStream_t stream);
 
-/* Per-phase GPU timing of thx_execute (tracing).  While enabled, each kernel
- * launch of an execution is bracketed by hipEvents recorded on the execution's
- * stream.  thx_plan_timings waits for the recorded events and writes, per
+/* Per-phase GPU timing of thx_execute (tracing).  thx_plan_enable_timing takes
+ * a mask of phases (bit 1 << THX_PHASE_x; THX_TIME_ALL for every phase, 0 to
+ * stop): each kernel launch of a selected phase is then bracketed by two
+ * hipEvents recorded on the execution's stream.  Every recorded event delays
+ * the stream by a few microseconds, so a measurement of one kernel should
+ * select that phase only.  thx_plan_timings waits for the recorded events and writes, per
  * phase, the summed milliseconds and the number of timed launches since the
  * last reset (ms and launches: host arrays of THX_NPHASES entries, either may
  * be NULL); reset != 0 clears the record.  At most 16384 launches are recorded
@@ -241,7 +244,8 @@ enum {
     THX_PHASE_SCAN = 9,     /* unit step by suffix sums (path 4)                    */
     THX_NPHASES = 10
 };
-thx_status thx_plan_enable_timing(thx_plan *plan, int enable);
+#define THX_TIME_ALL ((1u << THX_NPHASES) - 1u)
+thx_status thx_plan_enable_timing(thx_plan *plan, uint32_t phases);
 thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);
 
 const char *thx_status_string(thx_status s);

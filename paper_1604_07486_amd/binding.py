@@ -59,7 +59,7 @@ _sig("thx_lag2lag", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes
 _sig("thx_cache_clear", ctypes.c_int)
 _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
-_sig("thx_plan_enable_timing", ctypes.c_int, _vp, ctypes.c_int)
+_sig("thx_plan_enable_timing", ctypes.c_int, _vp, ctypes.c_uint32)
 _sig("thx_plan_timings", ctypes.c_int, _vp, _dp, ctypes.POINTER(_i64), ctypes.c_int)
 _sig("thx_batch_create", ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_int, _dp, ctypes.c_int,
      ctypes.POINTER(_i64), _i64, _dbl, ctypes.c_int, ctypes.c_uint32, _vp)
@@ -117,6 +117,8 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
+        if _lib is None:  # interpreter shutdown: the process exit releases the device memory
+            return
         if h is not None and h.value:
             _lib.thx_plan_destroy(h)
             self._h = _vp()
@@ -169,8 +171,12 @@ class Plan:
                                      _stream(stream)), "thx_plan_factors")
         return ell, piv[:max(K, 0)]
 
-    def enable_timing(self, on: bool = True):
-        _check(_lib.thx_plan_enable_timing(self._h, 1 if on else 0), "thx_plan_enable_timing")
+    def enable_timing(self, on: bool = True, phases=None):
+        """Time every phase (phases=None) or only the named ones (names from PHASES)."""
+        mask = 0
+        if on:
+            mask = (1 << len(PHASES)) - 1 if phases is None else sum(1 << PHASES.index(p) for p in set(phases))
+        _check(_lib.thx_plan_enable_timing(self._h, mask), "thx_plan_enable_timing")
 
     def timings(self, reset: bool = True):
         """{phase: (total_ms, launches)} of the timed executions since the last reset."""
@@ -211,6 +217,8 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
+        if _lib is None:  # interpreter shutdown: the process exit releases the device memory
+            return
         if h is not None and h.value:
             _lib.thx_batch_destroy(h)
             self._h = _vp()

@@ -442,39 +442,63 @@ template void launch_pack<float>(const KindDesc &, const int64_t *, const int64_
 // When L = 2n - 2 for a half of size n, the correlation picks up exactly one
 // extra term t_{n-1} z_0 at output n-1; it is removed here in double precision:
 //   w_{n-1} -= t_{n-1} v_0 sum_s l~_s[n-1] l~_s[0].
+// One thread per complex lane: parity kinds write both halves' outputs
+// (2a, 2a + 1) of lane a, the others output a (the sum of its two packed
+// ranks).  The G partial results are loaded four at a time and added in
+// group order.
 template <typename T>
-__global__ void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld, double *beta,
-                         int64_t N0, const cpx<T> *W, int G, int64_t nc, int64_t batch, int64_t L,
-                         const double *ell64, int64_t nc_ell, int S, const double *tsym,
-                         const double *row0)
+__global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                                double *beta, int64_t N0, const cpx<T> *W, int G, int64_t nc,
+                                                int64_t batch, int64_t L, const double *ell64, int64_t nc_ell,
+                                                int S, const double *tsym, const double *row0)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = blockIdx.y;
     int64_t base, N;
     vec_of(vr, b, ld, N0, base, N);
-    if (j > N) return;
+    if (a > (k.parity ? N / 2 : N)) return;
     const double *al = alpha + base;
-    double w = 0.0;
-    if (k.parity) {
-        const int64_t a = j >> 1;
-        const int q = (int)(j & 1);
-        for (int g = 0; g < G; ++g) {
-            const cpx<T> v = W[((int64_t)g * batch + b) * nc + a];
-            w += q ? (double)v.y : (double)v.x;
+    const cpx<T> *Wa = W + b * nc + a;
+    const int64_t gstride = batch * nc;
+    double wx = 0.0, wy = 0.0, wsum = 0.0;
+    int g = 0;
+    for (; g + 4 <= G; g += 4) {
+        cpx<T> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = Wa[(int64_t)(g + u) * gstride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            wx += (double)v[u].x;
+            wy += (double)v[u].y;
+            wsum += (double)v[u].x + (double)v[u].y;
         }
-        const int64_t nq = q ? (N + 1) / 2 : N / 2 + 1;
-        if (2 * nq - 2 == L && a == nq - 1) {
-            double gs = 0.0;
-            for (int s = 0; s < S; ++s)
-                gs = fma(ell64[2 * ((int64_t)s * nc_ell + nq - 1) + q], ell64[2 * ((int64_t)s * nc_ell) + q], gs);
-            w -= tsym[nq - 1] * gs * (d2_of(k, q) * al[q]);
+    }
+    for (; g < G; ++g) {
+        const cpx<T> v = Wa[(int64_t)g * gstride];
+        wx += (double)v.x;
+        wy += (double)v.y;
+        wsum += (double)v.x + (double)v.y;
+    }
+    if (k.parity) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int64_t j = 2 * a + q;
+            if (j > N) break;
+            double w = q ? wy : wx;
+            const int64_t nq = q ? (N + 1) / 2 : N / 2 + 1;
+            if (2 * nq - 2 == L && a == nq - 1) {
+                double gs = 0.0;
+                for (int s = 0; s < S; ++s)
+                    gs = fma(ell64[2 * ((int64_t)s * nc_ell + nq - 1) + q], ell64[2 * ((int64_t)s * nc_ell) + q], gs);
+                w -= tsym[nq - 1] * gs * (d2_of(k, q) * al[q]);
+            }
+            double out = d1_of(k, j) * w;
+            if (row0 && j == 0) out = row0[b];
+            beta[base + j] = out;
         }
     } else {
-        for (int g = 0; g < G; ++g) {
-            const cpx<T> v = W[((int64_t)g * batch + b) * nc + j];
-            w += (double)v.x + (double)v.y;
-        }
-        const int64_t n = N + 1;
+        const int64_t j = a, n = N + 1;
+        double w = wsum;
         if (2 * n - 2 == L && j == n - 1) {
             double gs = 0.0;
             for (int s = 0; s < S; ++s) {
@@ -484,10 +508,10 @@ __global__ void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
             }
             w -= tsym[n - 1] * gs * (d2_of(k, 0) * al[0]);
         }
+        double out = d1_of(k, j) * w;
+        if (row0 && j == 0) out = row0[b];
+        beta[base + j] = out;
     }
-    double out = d1_of(k, j) * w;
-    if (row0 && j == 0) out = row0[b];
-    beta[base + j] = out;
 }
 
 template <typename T>
@@ -497,7 +521,8 @@ void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, co
                    const double *tsym, const double *row0, hipStream_t s)
 {
     const int nt = 256;
-    dim3 grid((unsigned)((N + 1 + nt - 1) / nt), (unsigned)batch);
+    const int64_t lanes = k.parity ? N / 2 + 1 : N + 1;
+    dim3 grid((unsigned)((lanes + nt - 1) / nt), (unsigned)batch);
     k_unpack<T><<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, (const cpx<T> *)Wpart, G,
                                     nc, batch, L, ell64, nc_ell, S, tsym, row0);
 }
@@ -635,17 +660,20 @@ void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s)
 // ============================================================================
 constexpr int SC_NT = 256, SC_PER = 8, SC_CH = SC_NT * SC_PER;
 
-__device__ __forceinline__ void sc_lane(const KindDesc &k, const double *al, int64_t N, int64_t q, double &x,
-                                        double &y)
+// (D2 alpha) at the two components of lane q (returned by value: conditional
+// writes through references made the compiler keep the pair in scratch memory)
+struct Pair {
+    double x, y;
+};
+__device__ __forceinline__ Pair sc_lane(const KindDesc &k, const double *al, int64_t N, int64_t q)
 {
-    x = y = 0.0;
     if (k.parity) {
         const int64_t j0 = 2 * q, j1 = 2 * q + 1;
-        if (j0 <= N) x = d2_of(k, j0) * al[j0];
-        if (j1 <= N) y = d2_of(k, j1) * al[j1];
-    } else if (q <= N) {
-        x = d2_of(k, q) * al[q];
+        const double x = j0 <= N ? d2_of(k, j0) * al[j0] : 0.0;
+        const double y = j1 <= N ? d2_of(k, j1) * al[j1] : 0.0;
+        return Pair{x, y};
     }
+    return Pair{q <= N ? d2_of(k, q) * al[q] : 0.0, 0.0};
 }
 
 __device__ __forceinline__ void block_sum2(double &x, double &y, double *sx, double *sy)
@@ -681,10 +709,9 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, con
     double x = 0.0, y = 0.0;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
-        double u, v;
-        sc_lane(k, al, N, (int64_t)c * SC_CH + threadIdx.x + SC_NT * i, u, v);
-        x += u;
-        y += v;
+        const Pair u = sc_lane(k, al, N, (int64_t)c * SC_CH + threadIdx.x + SC_NT * i);
+        x += u.x;
+        y += u.y;
     }
     block_sum2(x, y, sx, sy);
     if (threadIdx.x == 0) {
@@ -715,10 +742,9 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
     const int64_t q0 = (int64_t)c * SC_CH;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
-        double u, v;
-        sc_lane(k, al, N, q0 + t + SC_NT * i, u, v);
-        lx[sc_pad(t + SC_NT * i)] = u;
-        ly[sc_pad(t + SC_NT * i)] = v;
+        const Pair u = sc_lane(k, al, N, q0 + t + SC_NT * i);
+        lx[sc_pad(t + SC_NT * i)] = u.x;
+        ly[sc_pad(t + SC_NT * i)] = u.y;
     }
     // carry: everything after this chunk
     double cx = 0.0, cy = 0.0;
@@ -921,19 +947,30 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
 {
     using F = RegFFT<T, L, 1, nthreads<L, 1>(), RMAX>;
     constexpr int E = F::E;
+    // Only positions below n <= L/2 + 1 are loaded or kept.  In the forward
+    // input layout (= the inverse's output layout) slot e holds position
+    // w + r L/RF (r = e mod RF, w < L/RF): slots with r > RF/2 are always zero
+    // on input and discarded on output; slot RF/2 of thread 0 holds position
+    // L/2, the only one of them that can be below n.
+    constexpr int RF = F::R_FIRST, RH = RF / 2;
+    static_assert(RF >= 2, "first radix");
+    constexpr int EH = (E / RF) * RH;
     __shared__ cpx<T> lds[F::LDS];
     const int g = blockIdx.x;
     const int64_t b = blockIdx.y;
     const int s0 = g * spg;
     const int s1 = min(S, s0 + spg);
-    cpx<T> acc[E], v[E];
+    cpx<T> acc[EH], accm{0, 0}, v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
+    for (int h = 0; h < EH; ++h) acc[h] = cpx<T>{0, 0};
+    int pmid, cmid;
+    F::in_pos(RH, pmid, cmid);
     // In double precision the packed input, the symbol and l~_s are read again
     // where they are used (cache hits) rather than kept live across the
     // transforms: opaque pointers stop the loads from being hoisted out of the
-    // slot loop (fewer registers; measured faster for FP64 only).
-    auto opq = [](const cpx<T> *q) { return sizeof(T) == 8 ? opaque_ptr(q) : q; };
+    // slot loop (fewer registers; measured faster for FP64; in FP32 needed at
+    // 8192 points, where the hoisted values spill).
+    auto opq = [](const cpx<T> *q) { return sizeof(T) == 8 || L >= 8192 ? opaque_ptr(q) : q; };
     for (int s = s0; s < s1; ++s) {
         const cpx<T> *es = opq(ell + (int64_t)s * nc);
         const cpx<T> *Xb = opq(X + b * nc);
@@ -941,7 +978,7 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
         for (int e = 0; e < E; ++e) {
             int pos, c;
             F::in_pos(e, pos, c);
-            v[e] = pos < n ? cdiag(es[pos], Xb[pos]) : cpx<T>{0, 0};
+            v[e] = (e % RF <= RH && pos < n) ? cdiag(es[pos], Xb[pos]) : cpx<T>{0, 0};
         }
         F::forward(v, lds, tw);
         const cpx<T> *ts = opq(that);
@@ -954,19 +991,22 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
         F::inverse(v, lds, tw);
         es = opq(es);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int h = 0; h < EH; ++h) {
+            const int e = (h / RH) * RF + h % RH;
             int pos, c;
             F::in_pos(e, pos, c);
-            if (pos < n) acc[e] = cadd(acc[e], cdiag(es[pos], v[e]));
+            if (pos < n) acc[h] = cadd(acc[h], cdiag(es[pos], v[e]));
         }
+        if (pmid < n) accm = cadd(accm, cdiag(es[pmid], v[RH]));
     }
     cpx<T> *Wg = W + ((int64_t)g * batch + b) * nc;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int h = 0; h < EH; ++h) {
         int pos, c;
-        F::in_pos(e, pos, c);
-        if (pos < n) Wg[pos] = acc[e];
+        F::in_pos((h / RH) * RF + h % RH, pos, c);
+        if (pos < n) Wg[pos] = acc[h];
     }
+    if (pmid < n) Wg[pmid] = accm;
 }
 
 template <typename T, int L>
@@ -1006,6 +1046,7 @@ bool launch_toep_lds(int64_t L, const void *X, int64_t nc, int64_t n, const void
                      int spg, int G, const void *that, const void *tw, void *W, int64_t batch,
                      hipStream_t s)
 {
+    if (n > L / 2 + 1 || n > nc) return false; // the kernel loads and keeps positions below L/2 + 1 only
     switch (L) {
 #define THX_CASE(LL) case LL: run_toep_lds<T, LL>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s); return true;
         THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
@@ -1129,7 +1170,8 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
         int a2, c;
         F::in_pos(e, a2, c);
         const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-        if (es) v[e] = a < n ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
+        // slots e with e mod RF > RF/2 hold positions above L/2: zero padding
+        if (es) v[e] = (e % F::R_FIRST <= F::R_FIRST / 2 && a < n) ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
         else v[e] = src[a];
     }
     F::forward(v, lds, twL2);
@@ -1234,18 +1276,36 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
 {
     constexpr int TC = mp_tc<T, L2>();
     using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
-    constexpr int64_t L = (int64_t)L1 * L2;
     constexpr int E = F::E;
+    // Outputs kept: positions a < n <= L/2 + 1 of each sequence.  In the
+    // inverse's output layout, register slot e holds column position
+    // j + r L2/RF (r = e mod RF, j < L2/RF), so the slots with r < RF/2 cover
+    // positions below L2/2 and only those are accumulated; the single output
+    // at a = L/2 (column position L2/2 of column 0: slot RF/2 of thread 0 in
+    // workgroup 0) has an accumulator of its own.
+    constexpr int RF = F::R_FIRST, RH = RF / 2;
+    static_assert(RF >= 2, "first radix");
+    constexpr int EH = (E / RF) * RH;
+    // l~_s is read with the tile (one memory round trip per slot) in single
+    // precision, and in double precision for columns of 512 (measured faster
+    // there; slower at 256, and it spills at 16, 32, 128 and 1024).
+    constexpr bool EARLY = sizeof(T) == 4 || L2 == 512;
     __shared__ cpx<T> lds[F::LDS];
     const int a1_0 = blockIdx.x * TC;
     const int g = blockIdx.y;
     const int64_t b = blockIdx.z;
-    cpx<T> acc[E], v[E];
+    auto kept_pos = [&](int h) {
+        int a2, c;
+        F::in_pos((h / RH) * RF + h % RH, a2, c);
+        return a1_0 + c + (int64_t)L1 * a2;
+    };
+    const int64_t amid = (int64_t)L1 * (L2 / 2) + (blockIdx.x == 0 && threadIdx.x == 0 ? 0 : n);
+    cpx<T> acc[EH], accm{0, 0}, v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = cpx<T>{0, 0};
+    for (int h = 0; h < EH; ++h) acc[h] = cpx<T>{0, 0};
     const int s1 = min(nslots, (g + 1) * spg);
     for (int sl = g * spg; sl < s1; ++sl) {
-        const cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
+        const cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L1 * L2;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int k2, c;
@@ -1253,39 +1313,35 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
             v[e] = ld_stream(Ub + a1_0 + c + (int64_t)L1 * k2);
         }
         const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
-        if constexpr (sizeof(T) == 4) {
-            // l~_s read with the tile: one memory round trip per slot (in double
-            // precision the extra registers spill, and it measured slower)
-            cpx<T> el[E];
+        if constexpr (EARLY) {
+            cpx<T> el[EH];
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                int a2, c;
-                F::in_pos(e, a2, c);
-                const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-                el[e] = a < n ? es[a] : cpx<T>{0, 0};
+            for (int h = 0; h < EH; ++h) {
+                const int64_t a = kept_pos(h);
+                el[h] = a < n ? es[a] : cpx<T>{0, 0};
             }
+            const cpx<T> elm = amid < n ? es[amid] : cpx<T>{0, 0};
             F::inverse(v, lds, twL2);
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cdiag(el[e], v[e]));
+            for (int h = 0; h < EH; ++h) acc[h] = cadd(acc[h], cdiag(el[h], v[(h / RH) * RF + h % RH]));
+            accm = cadd(accm, cdiag(elm, v[RH]));
         } else {
             F::inverse(v, lds, twL2);
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                int a2, c;
-                F::in_pos(e, a2, c);
-                const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-                if (a < n) acc[e] = cadd(acc[e], cdiag(es[a], v[e]));
+            for (int h = 0; h < EH; ++h) {
+                const int64_t a = kept_pos(h);
+                if (a < n) acc[h] = cadd(acc[h], cdiag(es[a], v[(h / RH) * RF + h % RH]));
             }
+            if (amid < n) accm = cadd(accm, cdiag(es[amid], v[RH]));
         }
     }
     cpx<T> *Wg = W + ((int64_t)(gofs + g) * batch + b) * nc;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        int a2, c;
-        F::in_pos(e, a2, c);
-        const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-        if (a < n) Wg[a] = acc[e];
+    for (int h = 0; h < EH; ++h) {
+        const int64_t a = kept_pos(h);
+        if (a < n) Wg[a] = acc[h];
     }
+    if (amid < n) Wg[amid] = accm;
 }
 
 // Column lengths instantiated for each row length (L1 L2 <= MP_LMAX).
@@ -1320,6 +1376,7 @@ bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, 
                   int slot0, int nslots, const void *src, void *U, int64_t batch, const void *twL2,
                   const void *twA, hipStream_t s)
 {
+    if (ell && (n > g.L1 * g.L2 / 2 + 1 || n > nc)) return false; // zero padding above L/2 is assumed
     if (g.L1 == mp_row_short<T>())
         return mp_p1_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, src, U, batch, twL2, twA, s);
     if (g.L1 == mp_row_long<T>())
@@ -1386,6 +1443,7 @@ bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, 
                   int slot0, int nslots, int spg, int G, void *Wpart, int gofs, int64_t batch,
                   const void *twL2, hipStream_t s)
 {
+    if (n > g.L1 * g.L2 / 2 + 1 || n > nc) return false; // the kernel keeps outputs below L/2 + 1 only
     if (g.L1 == mp_row_short<T>())
         return mp_p3_l2<T, (int)mp_row_short<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch, twL2, s);
     if (g.L1 == mp_row_long<T>())

@@ -173,7 +173,7 @@ struct thx_plan {
     int64_t U_slots = 0;
     int Gmax = 0;
     // per-phase event timing
-    bool timing = false;
+    uint32_t timing = 0; // bit i: phase i is timed
     std::vector<hipEvent_t> ev_pool;
     struct Mark {
         int phase;
@@ -750,7 +750,7 @@ struct PhaseTimer {
     hipEvent_t a = nullptr, b = nullptr;
     PhaseTimer(thx_plan *p_, int ph, hipStream_t s_) : p(p_), s(s_), phase(ph)
     {
-        if (!p->timing || p->marks.size() >= MAX_MARKS) return;
+        if (!((p->timing >> ph) & 1u) || p->marks.size() >= MAX_MARKS) return;
         const size_t need = 2 * (p->marks.size() + 1);
         while (p->ev_pool.size() < need) {
             hipEvent_t e;
@@ -1482,10 +1482,10 @@ thx_status thx_plan_autotune(thx_plan *plan, int64_t batch, hipStream_t stream)
     return autotune(plan, batch, stream);
 }
 
-thx_status thx_plan_enable_timing(thx_plan *p, int enable)
+thx_status thx_plan_enable_timing(thx_plan *p, uint32_t phases)
 {
     if (!p) return THX_INVALID_ARGUMENT;
-    p->timing = enable != 0;
+    p->timing = phases & ((1u << THX_NPHASES) - 1u);
     return THX_OK;
 }
 

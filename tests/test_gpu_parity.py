@@ -647,3 +647,38 @@ def test_jac2cheb_full_size_polynomial_identity(thx):
     err = float(np.max(np.abs(lhs - rhs)) / np.sum(np.abs(alpha)))
     print(f"  K={plan.rank} L={plan.fft_length} identity err={err:.3e}", flush=True)
     assert np.all(np.isfinite(beta)) and err < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Per-phase timing: the mask selects which launches carry events; timing does
+# not change the results.
+# ---------------------------------------------------------------------------
+
+def test_timing_phase_mask(thx):
+    import torch
+    N = 20000
+    print(f"[case] timing mask leg2cheb N={N}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=3)
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64)
+    a = _dev(alpha)
+    b0 = torch.empty_like(a)
+    plan.execute(a, b0)
+    plan.timings(reset=True)
+    plan.enable_timing(True, phases=("row",))
+    b1 = torch.empty_like(a)
+    for _ in range(3):
+        plan.execute(a, b1)
+    plan.enable_timing(False)
+    t = plan.timings(reset=True)
+    assert plan.path == 2
+    assert set(t) == {"row"} and t["row"][1] == 3 and t["row"][0] > 0
+    plan.enable_timing(True)
+    plan.execute(a, b1)
+    plan.enable_timing(False)
+    t = plan.timings(reset=True)
+    assert {"pack", "col_fwd", "row", "col_inv", "unpack"} <= set(t)
+    assert all(v[1] == 1 for v in t.values())
+    plan.execute(a, b1)
+    assert plan.timings(reset=True) == {}
+    torch.cuda.synchronize()
+    assert torch.equal(b0, b1)
