@@ -819,32 +819,37 @@ void launch_suffix(const KindDesc &k, const int64_t *off, const int64_t *deg, co
 // The matrix is an O(N^2) object anyway below the FFT crossover; materialised
 // once per plan, every execution is a contraction over k on the matrix cores:
 //   C[b][j] = sum_k alpha[b][k] At[k][j],   At[k][j] = A[j][k] = 0 for k < j.
-// Workgroup: 64 vectors x one chunk of up to 256 outputs; wave w owns vectors
-// 16w..16w+15 and all sixteen 16-column output tiles, so every wave has the
-// same (triangular) work between two barriers.  Chunks of 16 k of both
-// operands go through LDS; the next
-// chunk is read into registers while the matrix cores work on the current one.
+// Workgroup: 64 vectors x one chunk of up to 256 (or 64) outputs; wave w owns
+// vectors 16w..16w+15 and all 16-column output tiles of the chunk, so every
+// wave has the same (triangular) work between two barriers.  Chunks of 16 k of
+// both operands go through LDS; the next chunk is read into registers while
+// the matrix cores work on the current one.
 // v_mfma_f64_16x16x4f64 lane layout: operand a = X[m = lane&15][k = lane>>4],
 // operand b = Y[k = lane>>4][n = lane&15], result element i of a lane is
 // D[(lane>>4) + 4i][lane&15].
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int DN_BM = 64, DN_BN = 256, DN_BK = 16, DN_NT = 256;
+constexpr int DN_BM = 64, DN_BK = 16, DN_NT = 256;
 constexpr int DN_XW = DN_BK + 1;                // alpha tile row stride (doubles)
-constexpr int DN_AW = DN_BN + 16;               // matrix tile row stride: rows alternate LDS bank halves
 constexpr int DN_XL = DN_BM * DN_BK / DN_NT;    // alpha values per thread per chunk
-constexpr int DN_AL = DN_BK * DN_BN / DN_NT;    // matrix values per thread per chunk
-static_assert(DENSE_PAD % DN_BK == 0 && DN_BN % DN_BK == 0 && DN_XL * DN_NT == DN_BM * DN_BK, "dense tiling");
+static_assert(DENSE_PAD % DN_BK == 0 && DN_XL * DN_NT == DN_BM * DN_BK, "dense tiling");
 
+// BN outputs per workgroup: 256, or 64 when there are too few vectors to give
+// every CU a workgroup of 256 outputs
+template <int BN>
 __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
                                                  const double *__restrict__ alpha, int64_t ld,
                                                  double *__restrict__ beta, int64_t N0, int64_t batch)
 {
+    constexpr int AW = BN + 16;            // matrix tile row stride: rows alternate LDS bank halves
+    constexpr int AL = DN_BK * BN / DN_NT; // matrix values per thread per chunk
+    constexpr int AR = DN_NT / BN;         // chunk rows loaded in one sweep of the workgroup
+    static_assert(BN % DN_BK == 0 && AL * DN_NT == DN_BK * BN && AR * BN == DN_NT, "dense tiling");
     __shared__ double xs[DN_BM * DN_XW];
-    __shared__ double as[DN_BK * DN_AW];
+    __shared__ double as[DN_BK * AW];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t b0 = (int64_t)blockIdx.x * DN_BM;
-    const int j0 = blockIdx.y * DN_BN;
-    const int jend = min(npad, j0 + DN_BN);
+    const int j0 = blockIdx.y * BN;
+    const int jend = min(npad, j0 + BN);
     // alpha loader: chunk column xc, vector rows xr0 + 16 e
     const int xc = threadIdx.x % DN_BK, xr0 = threadIdx.x / DN_BK;
     int64_t lbase[DN_XL], ln[DN_XL];
@@ -854,9 +859,10 @@ __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, 
         if (b < batch) vec_of(vr, b, ld, N0, lbase[e], ln[e]);
         else lbase[e] = 0, ln[e] = -1;
     }
-    // matrix loader: output column j0 + threadIdx.x of chunk rows kc + e
-    const int aj = j0 + (int)threadIdx.x;
-    double xreg[DN_XL], areg[DN_AL];
+    // matrix loader: output column j0 + threadIdx.x % BN of chunk rows ar0 + AR e
+    const int ac = (int)threadIdx.x % BN, ar0 = (int)threadIdx.x / BN;
+    const int aj = j0 + ac;
+    double xreg[DN_XL], areg[AL];
     auto fetch = [&](int kc) {
 #pragma unroll
         for (int e = 0; e < DN_XL; ++e) {
@@ -864,13 +870,13 @@ __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, 
             xreg[e] = k <= ln[e] ? alpha[lbase[e] + k] : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < DN_AL; ++e) {
-            const int k = kc + e;
+        for (int e = 0; e < AL; ++e) {
+            const int k = kc + ar0 + AR * e;
             // At[k][j] = 0 for j > k
             areg[e] = (aj < npad && aj <= k) ? At[(int64_t)k * npad + aj] : 0.0;
         }
     };
-    constexpr int NTL = DN_BN / 16; // output tiles per chunk
+    constexpr int NTL = BN / 16; // output tiles per chunk
     v4d acc[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) acc[t] = v4d{0, 0, 0, 0};
@@ -881,7 +887,7 @@ __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, 
 #pragma unroll
         for (int e = 0; e < DN_XL; ++e) xs[(xr0 + (DN_NT / DN_BK) * e) * DN_XW + xc] = xreg[e];
 #pragma unroll
-        for (int e = 0; e < DN_AL; ++e) as[e * DN_AW + threadIdx.x] = areg[e];
+        for (int e = 0; e < AL; ++e) as[(ar0 + AR * e) * AW + ac] = areg[e];
         __syncthreads();
         if (kc + DN_BK < npad) fetch(kc + DN_BK);
 #pragma unroll
@@ -892,7 +898,7 @@ __global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, 
             for (int t = 0; t < NTL; ++t) {
                 const int jl = 16 * t;
                 if (j0 + jl >= jend || k0 + 4 <= j0 + jl) continue; // outside the matrix, or all zero there
-                const double bv = as[(ks + (lane >> 4)) * DN_AW + jl + (lane & 15)];
+                const double bv = as[(ks + (lane >> 4)) * AW + jl + (lane & 15)];
                 acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
             }
         }
@@ -920,8 +926,195 @@ void launch_dense(const double *At, int64_t npad, const int64_t *off, const int6
                   hipStream_t s)
 {
     if (batch <= 0) return;
-    dim3 grid((unsigned)((batch + DN_BM - 1) / DN_BM), (unsigned)((npad + DN_BN - 1) / DN_BN));
-    k_dense<<<grid, DN_NT, 0, s>>>(At, (int)npad, VecRef{off, deg}, alpha, ld, beta, N, batch);
+    const unsigned gx = (unsigned)((batch + DN_BM - 1) / DN_BM);
+    if ((int64_t)gx * ((npad + 255) / 256) >= 512) {
+        dim3 grid(gx, (unsigned)((npad + 255) / 256));
+        k_dense<256><<<grid, DN_NT, 0, s>>>(At, (int)npad, VecRef{off, deg}, alpha, ld, beta, N, batch);
+    } else {
+        dim3 grid(gx, (unsigned)((npad + 63) / 64));
+        k_dense<64><<<grid, DN_NT, 0, s>>>(At, (int)npad, VecRef{off, deg}, alpha, ld, beta, N, batch);
+    }
+}
+
+// ---- the same product in split bfloat16 (FP32-bulk plans) ------------------------
+// Every FP32 value is the exact sum of three bfloat16 parts x = h + m + l: h keeps
+// the top 8 significant bits (the low half of the encoding cleared), the
+// remainder x - h is exact in FP32 and has at most 16 significant bits, m keeps
+// its top 8, and the last remainder (at most 8 bits) is l; |m| < 2^-7 |x| and
+// |l| < 2^-14 |x|.  Of the nine partial products eight are summed on the matrix
+// cores in FP32, smallest first (every bfloat16 product is exact in FP32); the
+// dropped l l is below 2^-28 |a b|.  The result is an FP32-accurate product at
+// the bfloat16 rate of the matrix cores.
+//
+// v_mfma_f32_16x16x32_bf16 lane layout (lane l, m = l & 15, g = l >> 4):
+// operand a = X[m][8g .. 8g+7], operand b = Y[8g .. 8g+7][n = l & 15], result
+// element i = D[4g + i][l & 15].
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+constexpr int DB_VB = 64;  // vectors per workgroup: wave w owns vectors 16w .. 16w + 15
+constexpr int DB_NT = 256;
+constexpr int DB_KC = 32;  // k per chunk (one matrix-core step)
+static_assert(DENSE_PAD % DB_KC == 0, "dense padding");
+
+// the three parts of 8 consecutive values, packed two per dword (element 2i in
+// the low half): h, m, l
+__device__ __forceinline__ void split_bf16x3(const float *f, v4u &h, v4u &m, v4u &l)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned uh[2], um[2], ul[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const unsigned u = __float_as_uint(f[2 * i + q]);
+            uh[q] = u & 0xffff0000u;
+            const float r1 = f[2 * i + q] - __uint_as_float(uh[q]);
+            um[q] = __float_as_uint(r1) & 0xffff0000u;
+            const float r2 = r1 - __uint_as_float(um[q]);
+            ul[q] = __float_as_uint(r2) & 0xffff0000u;
+        }
+        h[i] = (uh[0] >> 16) | uh[1];
+        m[i] = (um[0] >> 16) | um[1];
+        l[i] = (ul[0] >> 16) | ul[1];
+    }
+}
+
+// Bp[((kc * 3 + part) * npad + j) * 32 + kk] = part of At[32 kc + kk][j]: a
+// lane's eight consecutive k of one column are one 16-byte load
+__global__ void k_split_matrix(const double *__restrict__ At, int npad, v4u *__restrict__ Bp)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; // (j, kc, kg)
+    const int nkc = npad / DB_KC;
+    if (q >= (int64_t)npad * nkc * 4) return;
+    const int kg = (int)(q & 3);
+    const int kc = (int)((q >> 2) % nkc);
+    const int j = (int)((q >> 2) / nkc);
+    float f[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = (float)At[(int64_t)(DB_KC * kc + 8 * kg + i) * npad + j];
+    v4u h, m, l;
+    split_bf16x3(f, h, m, l);
+    const int64_t base = ((int64_t)kc * 3 * npad + j) * 4 + kg; // in 16-byte units
+    Bp[base] = h;
+    Bp[base + (int64_t)npad * 4] = m;
+    Bp[base + (int64_t)npad * 8] = l;
+}
+
+// Workgroup: 64 vectors x JB outputs (JB = 256, or 64 when there are too few
+// vectors to give every CU a workgroup of 256 outputs).  Per chunk of 32 k the
+// workgroup stages the matrix parts of its JB columns in LDS (coalesced 16-byte
+// loads, read into registers one chunk ahead); each wave reads the alpha values
+// of its own 16 vectors straight into operand registers (also one chunk ahead),
+// splits them, and runs 8 products per output tile of the chunk.
+template <int JB>
+__global__ __launch_bounds__(DB_NT) void k_dense_bf16(const v4u *__restrict__ Bp, int npad, VecRef vr,
+                                                      const double *__restrict__ alpha, int64_t ld,
+                                                      double *__restrict__ beta, int64_t N0, int64_t batch)
+{
+    constexpr int NTL = JB / 16;               // output tiles
+    constexpr int BU = 3 * JB * 4;             // 16-byte units of one chunk's matrix parts
+    constexpr int BL = BU / DB_NT;             // of them per thread
+    static_assert(BL * DB_NT == BU, "matrix chunk loader");
+    __shared__ v4u bs[BU];                     // [part][column][k group]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t b0 = (int64_t)blockIdx.x * DB_VB;
+    const int j0 = blockIdx.y * JB;
+    const int jn = min(JB, npad - j0);          // columns of this workgroup inside the matrix
+    int64_t abase, an;
+    if (b0 + 16 * w + m < batch) vec_of(vr, b0 + 16 * w + m, ld, N0, abase, an);
+    else abase = 0, an = -1;
+    double xr[8];
+    v4u br[BL];
+    auto fetch = [&](int kc) {
+        const int64_t k0 = (int64_t)DB_KC * kc + 8 * g;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xr[i] = k0 + i <= an ? alpha[abase + k0 + i] : 0.0;
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+            const int u = (int)threadIdx.x + DB_NT * e; // (part, column, k group)
+            const int p = u / (JB * 4), r = u % (JB * 4);
+            br[e] = (r >> 2) < jn ? Bp[((int64_t)(kc * 3 + p) * npad + j0) * 4 + r] : v4u{0, 0, 0, 0};
+        }
+    };
+    v4f acc[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) acc[t] = v4f{0, 0, 0, 0};
+    const int nkc = npad / DB_KC;
+    // chunks of k below the first output are zero (At[k][j] = 0 for k < j)
+    fetch(j0 / DB_KC);
+    for (int kc = j0 / DB_KC; kc < nkc; ++kc) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < BL; ++e) bs[threadIdx.x + DB_NT * e] = br[e];
+        float f[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f[i] = (float)xr[i];
+        __syncthreads();
+        if (kc + 1 < nkc) fetch(kc + 1);
+        v4u xh, xm, xl;
+        split_bf16x3(f, xh, xm, xl);
+        const v8bf ah = __builtin_bit_cast(v8bf, xh), am = __builtin_bit_cast(v8bf, xm),
+                   al = __builtin_bit_cast(v8bf, xl);
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+            const int jl = 16 * t;
+            // outside the matrix, or every k of the chunk below the tile
+            if (jl >= jn || DB_KC * kc + DB_KC <= j0 + jl) continue;
+            const v8bf bh = __builtin_bit_cast(v8bf, bs[(0 * JB + jl + m) * 4 + g]);
+            const v8bf bm = __builtin_bit_cast(v8bf, bs[(1 * JB + jl + m) * 4 + g]);
+            const v8bf bl = __builtin_bit_cast(v8bf, bs[(2 * JB + jl + m) * 4 + g]);
+            v4f c = acc[t];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bm, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+        }
+    }
+    int64_t sbase[4], sn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t b = b0 + 16 * w + 4 * g + r;
+        if (b < batch) vec_of(vr, b, ld, N0, sbase[r], sn[r]);
+        else sbase[r] = 0, sn[r] = -1;
+    }
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+        if (16 * t >= jn) continue;
+        const int64_t j = j0 + 16 * t + m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (j <= sn[r]) beta[sbase[r] + j] = (double)acc[t][r];
+    }
+}
+
+int64_t dense_bf16_elems(int64_t npad) { return 3 * npad * npad; }
+
+void launch_split_matrix(const double *At, int64_t npad, void *Bp, hipStream_t s)
+{
+    const int64_t n = npad * (npad / DB_KC) * 4;
+    k_split_matrix<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(At, (int)npad, (v4u *)Bp);
+}
+
+void launch_dense_bf16(const void *Bp, int64_t npad, const int64_t *off, const int64_t *deg,
+                       const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
+                       hipStream_t s)
+{
+    if (batch <= 0) return;
+    const unsigned gx = (unsigned)((batch + DB_VB - 1) / DB_VB);
+    if ((int64_t)gx * ((npad + 255) / 256) >= 512) {
+        dim3 grid(gx, (unsigned)((npad + 255) / 256));
+        k_dense_bf16<256><<<grid, DB_NT, 0, s>>>((const v4u *)Bp, (int)npad, VecRef{off, deg}, alpha, ld,
+                                                 beta, N, batch);
+    } else {
+        dim3 grid(gx, (unsigned)((npad + 63) / 64));
+        k_dense_bf16<64><<<grid, DB_NT, 0, s>>>((const v4u *)Bp, (int)npad, VecRef{off, deg}, alpha, ld,
+                                                beta, N, batch);
+    }
 }
 
 // ============================================================================

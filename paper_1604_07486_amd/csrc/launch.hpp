@@ -135,6 +135,14 @@ constexpr int64_t DENSE_TUNE_MAX = 2048; // largest degree + 1 the autotuner tri
 void launch_dense(const double *At, int64_t npad, const int64_t *off, const int64_t *deg,
                   const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
                   hipStream_t s);
+// FP32-bulk plans: the matrix as three bfloat16 parts (dense_bf16_elems(npad)
+// 16-bit values, written by launch_split_matrix from At) and the product on the
+// bfloat16 matrix cores with FP32 accumulation
+int64_t dense_bf16_elems(int64_t npad);
+void launch_split_matrix(const double *At, int64_t npad, void *Bp, hipStream_t s);
+void launch_dense_bf16(const void *Bp, int64_t npad, const int64_t *off, const int64_t *deg,
+                       const double *alpha, int64_t ld, double *beta, int64_t N, int64_t batch,
+                       hipStream_t s);
 
 // ---- a5: Toeplitz products ---------------------------------------------------------
 // Largest length handled by one workgroup in LDS.  (Twice that, one workgroup

@@ -137,6 +137,7 @@ struct thx_plan {
     int path = 0;   // 0 direct, 1 LDS, 2 three-pass, 3 dense, 4 unit step (suffix sums)
     double *dense = nullptr; // path 3 (reported): At[k][j] = A[j][k], stride dense_ld; the
     int64_t dense_ld = 0;    // stages keep their own path for re-tuning
+    uint16_t *dense_bf = nullptr; // FP32-bulk: At split into three bfloat16 parts
     // launch shapes (workgroups targeted per launch), set by the autotuner
     int lds_blocks = 512;    // single-workgroup path: slot groups x vectors
     int p3_blocks = 1024;    // inverse column pass: column tiles x slot groups x vectors
@@ -215,6 +216,7 @@ struct thx_plan {
         dfree(tmp);
         dfree(tmp2);
         dfree(dense);
+        dfree(dense_bf);
         delete next;
     }
 };
@@ -637,6 +639,21 @@ void build_dense(thx_plan *p, hipStream_t s)
     p->tmp_elems = 0;
     p->dense = At;
     p->dense_ld = npad;
+    if (p->prec == THX_FP32_BULK) {
+        p->dense_bf = dalloc<uint16_t>(dense_bf16_elems(npad));
+        launch_split_matrix(At, npad, p->dense_bf, s);
+        launch_check();
+        hip_check(hipStreamSynchronize(s));
+    }
+}
+
+void drop_dense(thx_plan *p)
+{
+    dfree(p->dense);
+    dfree(p->dense_bf);
+    p->dense = nullptr;
+    p->dense_bf = nullptr;
+    p->dense_ld = 0;
 }
 
 thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
@@ -895,7 +912,8 @@ void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const dou
 {
     if (p->dense) {
         PhaseTimer t(p, THX_PHASE_DENSE, s);
-        launch_dense(p->dense, p->dense_ld, off, deg, alpha, ld, beta, degree, batch, s);
+        if (p->dense_bf) launch_dense_bf16(p->dense_bf, p->dense_ld, off, deg, alpha, ld, beta, degree, batch, s);
+        else launch_dense(p->dense, p->dense_ld, off, deg, alpha, ld, beta, degree, batch, s);
         launch_check();
         return;
     }
@@ -1066,19 +1084,18 @@ thx_status autotune(thx_plan *p, int64_t batch, hipStream_t s)
         for (const thx_plan *q = p; q; q = q->next) fft_capable |= q->path != 0;
         if (fft_capable && !(p->flags & (THX_FLAG_FORCE_FFT | THX_FLAG_NO_DENSE)) && n1 <= DENSE_TUNE_MAX) {
             double *keep = p->dense;
+            uint16_t *keep_bf = p->dense_bf;
             p->dense = nullptr;
+            p->dense_bf = nullptr;
             const float t_fft = time_launches([&] { execute_core(p, nullptr, nullptr, a, b, p->N, fb, n1, s, fb * n1); }, s);
             if (keep) {
                 p->dense = keep;
+                p->dense_bf = keep_bf;
             } else {
                 build_dense(p, s);
             }
             const float t_dense = time_launches([&] { execute_core(p, nullptr, nullptr, a, b, p->N, fb, n1, s, fb * n1); }, s);
-            if (t_fft < t_dense) {
-                dfree(p->dense);
-                p->dense = nullptr;
-                p->dense_ld = 0;
-            }
+            if (t_fft < t_dense) drop_dense(p);
         }
         hip_check(hipStreamSynchronize(s));
     } catch (const HipFail &f) {

@@ -289,7 +289,8 @@ def test_unit_step_full_size_sampled(thx):
 
 @pytest.mark.parametrize("l1,l2,N,prec", [(3.5, 0.5, 300, 0), (3.25, 0.5, 255, 1), (5.5, 0.75, 120, 0)])
 def test_ultra2ultra_chain_dense(thx, l1, l2, N, prec):
-    plan, _ = _check_full(thx, thx.ULTRA2ULTRA, N, prec, params=(l1, l2), seed=N, bar=TOL64, scale_bar=True)
+    plan, _ = _check_full(thx, thx.ULTRA2ULTRA, N, prec, params=(l1, l2), seed=N,
+                          bar=TOL64 if prec == 0 else TOL32, scale_bar=True)
     assert plan.path == 3
 
 
@@ -407,8 +408,8 @@ def test_batch_empty_and_bad_degree(thx):
 # ---------------------------------------------------------------------------
 # Dense path (path 3): the matrix is materialised once per plan from the
 # direct evaluation of the unit vectors; each execution is one matrix-core
-# product.  It computes in double precision for both precisions, so both are
-# held to the double-precision bar.
+# product, in double precision for THX_FP64 (held to the double-precision bar)
+# and in split bfloat16 with FP32 accumulation for THX_FP32_BULK.
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kind,params,N", [
@@ -420,22 +421,26 @@ def test_batch_empty_and_bad_degree(thx):
 ])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_dense_matches_oracle(thx, kind, params, N, prec):
-    plan, _ = _check_full(thx, kind, N, prec, params, flags=0, seed=N + kind, bar=TOL64,
-                          scale_bar=(kind == 2))
+    plan, err = _check_full(thx, kind, N, prec, params, flags=0, seed=N + kind, scale_bar=(kind == 2))
     assert plan.path == 3 and plan.fft_length == 0
+    if prec == 1:
+        # split bfloat16: FP32-level accuracy, far inside the FP32-bulk bar
+        assert err < 1e-6
 
 
-def test_dense_large_batch_subdegree_ld(thx):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dense_large_batch_subdegree_ld(thx, prec):
     import torch
     N, batch, ld = 100, 70000, 105                     # more vectors than one grid dimension holds
-    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64)
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64 if prec == 0 else EPS32, prec)
     assert plan.path == 3
     alpha = inputs.coeffs(ld - 1, 1.0, seed=21, batch=batch)
     a = _dev(alpha)
     rng = inputs.rng(22)
     pick = np.concatenate([[0, 1, batch - 1], rng.integers(0, batch, 61)])
+    bar = TOL64 if prec == 0 else TOL32
     for deg in (N, 60):
-        print(f"[case] dense batch={batch} ld={ld} degree={deg}", flush=True)
+        print(f"[case] dense batch={batch} ld={ld} degree={deg} prec={prec}", flush=True)
         b = torch.full_like(a, 7.0)
         plan.execute(a, b, degree=deg)
         b2 = torch.empty_like(a).copy_(b)
@@ -445,7 +450,7 @@ def test_dense_large_batch_subdegree_ld(thx):
         got = b.cpu().numpy()
         for i in pick:
             ref = oracle.matvec("leg2cheb", alpha[i, :deg + 1])
-            assert _err(got[i, :deg + 1], ref, alpha[i, :deg + 1]) < TOL64
+            assert _err(got[i, :deg + 1], ref, alpha[i, :deg + 1]) < bar
         assert np.all(got[:, deg + 1:] == 7.0)        # entries beyond the degree untouched
 
 
