@@ -54,7 +54,8 @@ typedef enum {
 typedef enum {
     THX_FP64 = 0,      /* every step in double precision                              */
     THX_FP32_BULK = 1  /* FFTs and rank accumulation in single precision; Lambda and
-                          Gamma ratios, the pivoted Cholesky and D1, D2 in double     */
+                          Gamma ratios, the pivoted Cholesky and D1, D2 in double;
+                          the dense path (3) in split bfloat16 with FP32 accumulation */
 } thx_precision;
 
 /* plan flags */
@@ -113,7 +114,9 @@ thx_status thx_plan_destroy(thx_plan *plan);
  * FFT, 2 three-pass FFT, 3 dense: below the FFT crossover (degree + 1 <= 512,
  * THX_FLAG_NO_DENSE not set) the plan materialises the (degree+1)^2 matrix once
  * by the direct evaluation of the unit vectors, and every execution is one
- * double-precision matrix-core product with it (both precisions), 4 unit step:
+ * matrix-core product with it (double precision for THX_FP64; for
+ * THX_FP32_BULK the matrix and alpha as exact sums of three bfloat16 parts,
+ * eight partial products summed in single precision), 4 unit step:
  * a parameter lowered by exactly 1 makes T and H constant (Sec. 5.2 and 5.3,
  * case 1), and beta_j = D1_j t_0 h_0 sum_{k >= j} D2_k alpha_k (k - j even for
  * the parity kinds) is a suffix sum, computed by a reverse scan in double
