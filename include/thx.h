@@ -137,6 +137,9 @@ thx_status thx_plan_fft_geometry(const thx_plan *plan, int64_t *rows, int64_t *c
  * the inverse column pass.  Any output pointer may be NULL;
  * THX_INVALID_ARGUMENT for a null plan. */
 thx_status thx_plan_launch_shape(const thx_plan *plan, int32_t *lds_blocks, int32_t *p3_blocks);
+/* Largest FFT radix (8 or 16) of the (first) stage's single-workgroup path, as
+ * set by thx_plan_autotune (default 8); -1 for a null plan. */
+int32_t thx_plan_lds_radix(const thx_plan *plan);
 /* Partial-sum groups the (first) stage uses for an execution of `batch` vectors
  * (the extra reads of the final D1 step); 0 for paths without them. */
 int32_t thx_plan_partial_groups(const thx_plan *plan, int64_t batch);

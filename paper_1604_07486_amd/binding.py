@@ -48,6 +48,7 @@ _sig("thx_plan_path", _i32, _vp)
 _sig("thx_plan_fft_geometry", ctypes.c_int, _vp, _p64, _p64, _p64)
 _sig("thx_plan_autotune", ctypes.c_int, _vp, _i64, _vp)
 _sig("thx_plan_launch_shape", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
+_sig("thx_plan_lds_radix", _i32, _vp)
 _sig("thx_plan_partial_groups", _i32, _vp, _i64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
@@ -141,6 +142,11 @@ class Plan:
         a, c = _i32(), _i32()
         _check(_lib.thx_plan_launch_shape(self._h, ctypes.byref(a), ctypes.byref(c)), "thx_plan_launch_shape")
         return a.value, c.value
+
+    @property
+    def lds_radix(self) -> int:
+        """Largest FFT radix of the single-workgroup path (set by autotune)."""
+        return int(_lib.thx_plan_lds_radix(self._h))
 
     def partial_groups(self, batch: int = 1) -> int:
         return int(_lib.thx_plan_partial_groups(self._h, int(batch)))

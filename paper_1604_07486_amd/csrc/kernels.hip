@@ -1124,21 +1124,23 @@ void launch_dense_bf16(const void *Bp, int64_t npad, const int64_t *off, const i
 // Largest radix of the register FFTs.  Radix 8 keeps 8 values per thread, so a
 // workgroup of M*NB/8 threads holds the transform: twice the waves of radix 16
 // at the same LDS footprint, which is what hides HBM latency in these passes.
+// The single-workgroup path also has radix 16 (half the threads, one LDS
+// exchange fewer at 4096 points); the autotuner picks per plan.
 constexpr int RMAX = 8;
-template <int M, int NB>
-constexpr int nthreads() { return fft_threads(M, NB, RMAX); }
+template <int M, int NB, int R = RMAX>
+constexpr int nthreads() { return fft_threads(M, NB, R); }
 
 // One workgroup per (slot group, vector): for each slot s of the group
 //   z = l~_s o X (zero-padded to L) -> FFT -> . that -> IFFT -> acc += l~_s o y
 // with `that` = FFT(symbol)/L.  The accumulator stays in registers, in the
 // forward-input layout that the inverse transform returns to.
-template <typename T, int L>
-__global__ __launch_bounds__((nthreads<L, 1>())) void k_toep_lds(
+template <typename T, int L, int R>
+__global__ __launch_bounds__((nthreads<L, 1, R>())) void k_toep_lds(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int S,
     int spg, const cpx<T> *__restrict__ that, const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ W,
     int64_t batch)
 {
-    using F = RegFFT<T, L, 1, nthreads<L, 1>(), RMAX>;
+    using F = RegFFT<T, L, 1, nthreads<L, 1, R>(), R>;
     constexpr int E = F::E;
     // Only positions below n <= L/2 + 1 are loaded or kept.  In the forward
     // input layout (= the inverse's output layout) slot e holds position
@@ -1224,38 +1226,47 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_fft_lds(const cpx<T> *in
     }
 }
 
-template <typename T, int L>
+template <typename T, int L, int R>
 static void run_toep_lds(const void *X, int64_t nc, int64_t n, const void *ell, int S, int spg, int G,
                          const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
 {
     dim3 grid((unsigned)G, (unsigned)batch);
-    k_toep_lds<T, L><<<grid, nthreads<L, 1>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
-                                                         S, spg, (const cpx<T> *)that,
-                                                         (const cpx<T> *)tw, (cpx<T> *)W, batch);
+    k_toep_lds<T, L, R><<<grid, nthreads<L, 1, R>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
+                                                               S, spg, (const cpx<T> *)that,
+                                                               (const cpx<T> *)tw, (cpx<T> *)W, batch);
+}
+
+template <typename T, int L>
+static void run_toep_lds_r(int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S, int spg,
+                           int G, const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
+{
+    if (radix == 16) run_toep_lds<T, L, 16>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
+    else run_toep_lds<T, L, 8>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
 }
 
 template <typename T>
-bool launch_toep_lds(int64_t L, const void *X, int64_t nc, int64_t n, const void *ell, int S,
+bool launch_toep_lds(int64_t L, int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S,
                      int spg, int G, const void *that, const void *tw, void *W, int64_t batch,
                      hipStream_t s)
 {
     if (n > L / 2 + 1 || n > nc) return false; // the kernel loads and keeps positions below L/2 + 1 only
+    if (radix != 8 && radix != 16) return false;
     switch (L) {
-#define THX_CASE(LL) case LL: run_toep_lds<T, LL>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s); return true;
+#define THX_CASE(LL) case LL: run_toep_lds_r<T, LL>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s); return true;
         THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
         THX_CASE(4096)
 #undef THX_CASE
     case 8192:
         if constexpr (sizeof(T) == 4) {
-            run_toep_lds<T, 8192>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
+            run_toep_lds_r<T, 8192>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
             return true;
         }
         return false;
     default: return false;
     }
 }
-template bool launch_toep_lds<double>(int64_t, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
-template bool launch_toep_lds<float>(int64_t, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
+template bool launch_toep_lds<double>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
+template bool launch_toep_lds<float>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
 
 template <typename T>
 bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale, hipStream_t s)

@@ -158,9 +158,10 @@ template <typename T> constexpr int64_t mp_row_short() { return sizeof(T) == 8 ?
 template <typename T> constexpr int64_t mp_row_long() { return sizeof(T) == 8 ? 4096 : 8192; }
 constexpr int64_t MP_LMAX = (int64_t)1 << 22;
 
-// single-workgroup path: W[g] = sum_{s in group g} ell_s o IFFT(FFT(ell_s o X) . that)
+// single-workgroup path: W[g] = sum_{s in group g} ell_s o IFFT(FFT(ell_s o X) . that),
+// largest FFT radix 8 or 16
 template <typename T>
-bool launch_toep_lds(int64_t L, const void *X, int64_t nc, int64_t n, const void *ell, int S,
+bool launch_toep_lds(int64_t L, int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S,
                      int slots_per_group, int G, const void *that, const void *tw, void *Wpart,
                      int64_t batch, hipStream_t s);
 // plain forward FFT of one length-L complex array in LDS (symbol transform), scaled

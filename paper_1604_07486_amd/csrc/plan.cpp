@@ -140,6 +140,7 @@ struct thx_plan {
     uint16_t *dense_bf = nullptr; // FP32-bulk: At split into three bfloat16 parts
     // launch shapes (workgroups targeted per launch), set by the autotuner
     int lds_blocks = 512;    // single-workgroup path: slot groups x vectors
+    int lds_radix = 8;       // single-workgroup path: largest FFT radix (8 or 16)
     int p3_blocks = 1024;    // inverse column pass: column tiles x slot groups x vectors
     int64_t nc = 0;  // complex lanes
     int64_t ncs = 0; // lane stride of the Cholesky columns, packed input and partial sums:
@@ -438,6 +439,8 @@ void build_fft(thx_plan *p, hipStream_t s)
     const int64_t lmax = f64 ? lds_max_len<double>() : lds_max_len<float>();
     if (L <= lmax) {
         p->path = 1;
+        // THX_LDS_RADIX: largest FFT radix of this path before any tuning (8 or 16)
+        if (const char *e = getenv("THX_LDS_RADIX")) p->lds_radix = atoi(e) == 16 ? 16 : 8;
         p->twL = make_twiddles(p, L, L, s, 0);
         if (f64) {
             p->that = spec;
@@ -841,7 +844,8 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
             PhaseTimer t(p, THX_PHASE_TOEP_LDS, s);
-            if (!launch_toep_lds<T>(p->L, p->X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL, p->Wp, batch, s))
+            if (!launch_toep_lds<T>(p->L, p->lds_radix, p->X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL,
+                                    p->Wp, batch, s))
                 throw HipFail{hipErrorInvalidValue};
         } else {
             const MultiPassGeom &g = p->geom;
@@ -1034,14 +1038,18 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
 {
     auto run = [&] { execute_stage(p, nullptr, nullptr, alpha, beta, p->N, batch, p->N + 1, s); };
     if (p->path == 1) {
-        int best = p->lds_blocks;
+        int best = p->lds_blocks, best_r = p->lds_radix;
         float tb = 1e30f;
-        for (int lb : {256, 512, 1024, 2048}) {
-            p->lds_blocks = lb;
-            const float t = time_launches(run, s);
-            if (t < tb) tb = t, best = lb;
+        for (int radix : {8, 16}) {
+            p->lds_radix = radix;
+            for (int lb : {256, 512, 1024, 2048}) {
+                p->lds_blocks = lb;
+                const float t = time_launches(run, s);
+                if (t < tb) tb = t, best = lb, best_r = radix;
+            }
         }
         p->lds_blocks = best;
+        p->lds_radix = best_r;
     } else if (p->path == 2) {
         const bool f64 = p->prec == THX_FP64;
         const int64_t rows[2] = {f64 ? mp_row_short<double>() : mp_row_short<float>(),
@@ -1377,6 +1385,7 @@ thx_status thx_plan_launch_shape(const thx_plan *p, int32_t *lds_blocks, int32_t
     if (p3_blocks) *p3_blocks = p->p3_blocks;
     return THX_OK;
 }
+int32_t thx_plan_lds_radix(const thx_plan *p) { return p ? p->lds_radix : -1; }
 
 int32_t thx_plan_partial_groups(const thx_plan *p, int64_t batch)
 {

@@ -158,6 +158,17 @@ def test_leg2cheb_row_lengths(thx, N, prec, row, monkeypatch):
     assert plan.path == 2
 
 
+# both FFT radices of the single-workgroup path (THX_LDS_RADIX is read at plan
+# creation; the autotuner chooses between them), every transform length
+@pytest.mark.parametrize("radix", [8, 16])
+@pytest.mark.parametrize("N,prec", [(40, 0), (100, 1), (200, 0), (500, 1), (1000, 0), (2000, 0), (4000, 1),
+                                    (4095, 0), (8190, 1)])
+def test_leg2cheb_lds_radix(thx, N, prec, radix, monkeypatch):
+    monkeypatch.setenv("THX_LDS_RADIX", str(radix))
+    plan, _ = _check_full(thx, thx.LEG2CHEB, N, prec, flags=thx.FLAG_FORCE_FFT, seed=N + radix)
+    assert plan.path == 1 and plan.lds_radix == radix
+
+
 @pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 511, 512])
 @pytest.mark.parametrize("dense", [True, False])
 def test_leg2cheb_direct(thx, N, dense):
@@ -241,6 +252,43 @@ def test_leg2cheb_full_size_sampled(thx, N, prec, p):
     print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} sampled err={err:.3e}", flush=True)
     assert np.all(np.isfinite(got))
     assert err < (TOL64 if prec == 0 else TOL32)
+
+
+def test_leg2cheb_full_size_clenshaw(thx):
+    # the two expansions are one polynomial: sum alpha_k P_k(x) = sum beta_k T_k(x)
+    # at 1000 seeded x in [-1, 1], both sides by Clenshaw (numpy's legval / chebval)
+    # in float64; this reaches every output row, not only the sampled ones.
+    # |dp(x)| <= ||d beta||_1, and the evaluation rounding is about N eps ||alpha||_1
+    # (1.2e-10 at N = 2^20), hence the bar.
+    import torch
+    from numpy.polynomial import chebyshev, legendre
+    N = 1 << 20
+    print(f"[case] leg2cheb N={N} Clenshaw at 1000 points", flush=True)
+    alpha = inputs.coeffs(N, 1.5, seed=20)
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64)
+    a = _dev(alpha)
+    b = torch.empty_like(a)
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    beta = b.cpu().numpy()
+    x = inputs.points(1000, seed=8)
+    err = float(np.max(np.abs(legendre.legval(x, alpha) - chebyshev.chebval(x, beta))) / np.sum(np.abs(alpha)))
+    print(f"  K={plan.rank} L={plan.fft_length} Clenshaw err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(beta)) and err < 1e-9
+
+
+def test_cheb2leg_full_size_sampled(thx):
+    # the reverse direction at N = 2^20 (FP64, Hankel parts to 1e-17): sampled rows,
+    # plus 32 rows around N/2, where the D1 ~ j and D2 ~ k scalings make the
+    # truncation error largest
+    N = 1 << 20
+    plan, alpha, got = _run(thx, thx.CHEB2LEG, N, thx.FP64, p=1.5, seed=21, tol=1e-17)
+    rows = np.unique(np.concatenate([inputs.sample_rows(N, 256, seed=19), N // 2 - 16 + np.arange(32)]))
+    ref = oracle.matvec("cheb2leg", alpha, rows=rows)
+    err = float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+    print(f"  K={plan.rank} L={plan.fft_length} path={plan.path} sampled err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < TOL64
 
 
 # ---------------------------------------------------------------------------
