@@ -140,6 +140,11 @@ thx_status thx_plan_launch_shape(const thx_plan *plan, int32_t *lds_blocks, int3
 /* Largest FFT radix (8 or 16) of the (first) stage's single-workgroup path, as
  * set by thx_plan_autotune (default 8); -1 for a null plan. */
 int32_t thx_plan_lds_radix(const thx_plan *plan);
+/* Workgroups targeted per launch of the (first) stage's forward column pass, as
+ * set by thx_plan_autotune: 0 (the default) is one workgroup per column tile,
+ * slot and vector; a positive value lets each workgroup transform its tile for
+ * several consecutive slots.  -1 for a null plan. */
+int32_t thx_plan_p1_blocks(const thx_plan *plan);
 /* Partial-sum groups the (first) stage uses for an execution of `batch` vectors
  * (the extra reads of the final D1 step); 0 for paths without them. */
 int32_t thx_plan_partial_groups(const thx_plan *plan, int64_t batch);

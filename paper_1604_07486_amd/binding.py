@@ -49,6 +49,7 @@ _sig("thx_plan_fft_geometry", ctypes.c_int, _vp, _p64, _p64, _p64)
 _sig("thx_plan_autotune", ctypes.c_int, _vp, _i64, _vp)
 _sig("thx_plan_launch_shape", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("thx_plan_lds_radix", _i32, _vp)
+_sig("thx_plan_p1_blocks", _i32, _vp)
 _sig("thx_plan_partial_groups", _i32, _vp, _i64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
@@ -142,6 +143,11 @@ class Plan:
         a, c = _i32(), _i32()
         _check(_lib.thx_plan_launch_shape(self._h, ctypes.byref(a), ctypes.byref(c)), "thx_plan_launch_shape")
         return a.value, c.value
+
+    @property
+    def p1_blocks(self) -> int:
+        """Workgroups targeted per forward column pass (0: one per tile, slot and vector)."""
+        return int(_lib.thx_plan_p1_blocks(self._h))
 
     @property
     def lds_radix(self) -> int:

@@ -1350,10 +1350,14 @@ __device__ __forceinline__ cpx<T> tw_L(const cpx<T> *__restrict__ twA, const cpx
     return cmul(twA[e & (L1 - 1)], twL2[e >> ilog2(L1)]);
 }
 
-template <typename T, int L1, int L2>
+// A workgroup transforms one column tile of one vector, for one slot (SG =
+// false, spb = 1) or for `spb` consecutive slots (SG = true: the packed-input
+// tile stays in registers across them; a separate instantiation, because the
+// values it keeps live would make the single-slot kernel spill at 1024 threads).
+template <typename T, int L1, int L2, bool SG>
 __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
-    int nslots, const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
+    int nslots, int spb, const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
     const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA)
 {
     constexpr int TC = mp_tc<T, L2>();
@@ -1362,47 +1366,79 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     constexpr int64_t L = (int64_t)L1 * L2;
     __shared__ cpx<T> lds[F::LDS];
     constexpr int tiles = L1 / TC;
+    constexpr int RF = F::R_FIRST;
     // tiles fastest: consecutive blocks write adjacent columns of the same rows
     const int a1_0 = (int)(blockIdx.x % tiles) * TC;
-    const int sl = (int)((blockIdx.x / tiles) % nslots);
-    const int64_t b = blockIdx.x / (tiles * nslots);
-    const cpx<T> *es = ell ? ell + (int64_t)(slot0 + sl) * nc : nullptr;
+    const int nsg = (nslots + spb - 1) / spb;
+    const int sg = (int)((blockIdx.x / tiles) % nsg);
+    const int64_t b = blockIdx.x / (tiles * nsg);
     const cpx<T> *Xb = X ? X + b * nc : nullptr;
-    cpx<T> v[F::E];
+    // slots e with e mod RF > RF/2 hold positions above L/2: zero padding
+    auto live = [&](int e, int64_t a) { return e % RF <= RF / 2 && a < n; };
+    auto transform_store = [&](cpx<T> *v, int sl) {
+        F::forward(v, lds, twL2);
+        cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
+        // Twiddle w_L^{a1 k2}.  The thread's column a1 is the same in all its
+        // butterfly groups p and its rows are k2 = j_p + q L2/RL, so the factor is
+        // w_L^{a1 j_p} (one table pair per group) times the q-th power of
+        // w_L^{a1 L2/RL} (powers of two from the tables, the rest as products).
+        constexpr int RL = F::R_LAST, PG = F::E / RL;
+        static_assert(NT % TC == 0, "column of a thread fixed across groups");
+        const int a1 = a1_0 + (int)threadIdx.x % TC;
+        cpx<T> st[RL];
+        st[0] = cpx<T>{1, 0};
 #pragma unroll
-    for (int e = 0; e < F::E; ++e) {
-        int a2, c;
-        F::in_pos(e, a2, c);
-        const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-        // slots e with e mod RF > RF/2 hold positions above L/2: zero padding
-        if (es) v[e] = (e % F::R_FIRST <= F::R_FIRST / 2 && a < n) ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
-        else v[e] = src[a];
-    }
-    F::forward(v, lds, twL2);
-    cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L;
-    // Twiddle w_L^{a1 k2}.  The thread's column a1 is the same in all its
-    // butterfly groups p and its rows are k2 = j_p + q L2/RL, so the factor is
-    // w_L^{a1 j_p} (one table pair per group) times the q-th power of
-    // w_L^{a1 L2/RL} (powers of two from the tables, the rest as products).
-    constexpr int RL = F::R_LAST, PG = F::E / RL;
-    static_assert(NT % TC == 0, "column of a thread fixed across groups");
-    const int a1 = a1_0 + (int)threadIdx.x % TC;
-    cpx<T> st[RL];
-    st[0] = cpx<T>{1, 0};
+        for (int q = 1; q < RL; ++q) {
+            if ((q & (q - 1)) == 0) st[q] = tw_L<T, L1>(twA, twL2, a1 * q * (L2 / RL));
+            else st[q] = cmul(st[q & (q - 1)], st[q & -q]);
+        }
 #pragma unroll
-    for (int q = 1; q < RL; ++q) {
-        if ((q & (q - 1)) == 0) st[q] = tw_L<T, L1>(twA, twL2, a1 * q * (L2 / RL));
-        else st[q] = cmul(st[q & (q - 1)], st[q & -q]);
-    }
+        for (int p = 0; p < PG; ++p) {
+            const int j = ((int)threadIdx.x + NT * p) / TC;
+            const cpx<T> bp = tw_L<T, L1>(twA, twL2, a1 * j);
 #pragma unroll
-    for (int p = 0; p < PG; ++p) {
-        const int j = ((int)threadIdx.x + NT * p) / TC;
-        const cpx<T> bp = tw_L<T, L1>(twA, twL2, a1 * j);
+            for (int q = 0; q < RL; ++q) {
+                const int k2 = j + q * (L2 / RL);
+                const cpx<T> t = q == 0 ? bp : cmul(bp, st[q]);
+                st_stream(Ub + a1 + (int64_t)L1 * k2, cmul(v[p * RL + q], t));
+            }
+        }
+    };
+    if constexpr (!SG) {
+        const int sl = sg;
+        const cpx<T> *es = ell ? ell + (int64_t)(slot0 + sl) * nc : nullptr;
+        cpx<T> v[F::E];
 #pragma unroll
-        for (int q = 0; q < RL; ++q) {
-            const int k2 = j + q * (L2 / RL);
-            const cpx<T> t = q == 0 ? bp : cmul(bp, st[q]);
-            st_stream(Ub + a1 + (int64_t)L1 * k2, cmul(v[p * RL + q], t));
+        for (int e = 0; e < F::E; ++e) {
+            int a2, c;
+            F::in_pos(e, a2, c);
+            const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+            if (es) v[e] = live(e, a) ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
+            else v[e] = src[a];
+        }
+        transform_store(v, sl);
+    } else {
+        const int s0 = sg * spb, s1 = min(nslots, s0 + spb);
+        cpx<T> xv[F::E];
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) {
+            int a2, c;
+            F::in_pos(e, a2, c);
+            const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+            xv[e] = live(e, a) ? Xb[a] : cpx<T>{0, 0};
+        }
+        for (int sl = s0; sl < s1; ++sl) {
+            const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
+            cpx<T> v[F::E];
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) {
+                int a2, c;
+                F::in_pos(e, a2, c);
+                const int64_t a = a1_0 + c + (int64_t)L1 * a2;
+                v[e] = live(e, a) ? cdiag(es[a], xv[e]) : cpx<T>{0, 0};
+            }
+            transform_store(v, sl);
+            __syncthreads(); // the next slot's transform reuses the LDS
         }
     }
 }
@@ -1553,18 +1589,23 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
 
 template <typename T, int L1>
 bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
-              int nslots, const void *src, void *U, int64_t batch, const void *twL2, const void *twA,
+              int nslots, int spb, const void *src, void *U, int64_t batch, const void *twL2, const void *twA,
               hipStream_t s)
 {
+    const int nsg = (nslots + spb - 1) / spb;
     switch (g.L2) {
 #define THX_P1(LL2)                                                                                       \
     case LL2:                                                                                             \
         if constexpr ((int64_t)L1 * LL2 <= MP_LMAX) {                                                     \
-            k_mp_p1<T, L1, LL2><<<dim3((unsigned)(L1 / mp_tc<T, LL2>() * nslots * batch)),               \
-                                  mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell, \
-                                                           slot0, nslots, (const cpx<T> *)src,            \
-                                                           (cpx<T> *)U, batch, (const cpx<T> *)twL2,      \
-                                                           (const cpx<T> *)twA);                          \
+            const dim3 grid((unsigned)(L1 / mp_tc<T, LL2>() * nsg * batch));                               \
+            if (spb > 1)                                                                                  \
+                k_mp_p1<T, L1, LL2, true><<<grid, mp_nt<T, LL2>(), 0, s>>>(                               \
+                    (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, slot0, nslots, spb,                    \
+                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA);  \
+            else                                                                                          \
+                k_mp_p1<T, L1, LL2, false><<<grid, mp_nt<T, LL2>(), 0, s>>>(                              \
+                    (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, slot0, nslots, 1,                      \
+                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA);  \
             return true;                                                                                  \
         } else {                                                                                          \
             return false;                                                                                 \
@@ -1577,18 +1618,21 @@ bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, cons
 
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
-                  int slot0, int nslots, const void *src, void *U, int64_t batch, const void *twL2,
+                  int slot0, int nslots, int spb, const void *src, void *U, int64_t batch, const void *twL2,
                   const void *twA, hipStream_t s)
 {
     if (ell && (n > g.L1 * g.L2 / 2 + 1 || n > nc)) return false; // zero padding above L/2 is assumed
+    if (spb < 1 || nslots < 1 || (spb > 1 && !ell)) return false;
     if (g.L1 == mp_row_short<T>())
-        return mp_p1_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, src, U, batch, twL2, twA, s);
+        return mp_p1_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
+                                                    twA, s);
     if (g.L1 == mp_row_long<T>())
-        return mp_p1_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, src, U, batch, twL2, twA, s);
+        return mp_p1_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
+                                                   twA, s);
     return false;
 }
-template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
-template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
 
 template <typename T, int L1>
 void mp_p2_run(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,

@@ -175,10 +175,11 @@ struct MultiPassGeom {
 // geometry for length L; `row` selects mp_row_short / mp_row_long, any other
 // value (or one that leaves the columns outside 2..1024) the default
 template <typename T> MultiPassGeom multipass_geom(int64_t L, int64_t row = 0);
-// P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr)
+// P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr),
+// `spb` consecutive slots per workgroup
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
-                  int slot0, int nslots, const void *src, void *U, int64_t batch,
+                  int slot0, int nslots, int spb, const void *src, void *U, int64_t batch,
                   const void *twL2, const void *twA, hipStream_t s);
 // P2: row FFT, times permuted symbol, inverse row FFT, conjugate twiddle (full);
 // or forward row FFT only, scaled, written to `out` (symbol transform)

@@ -142,6 +142,8 @@ struct thx_plan {
     int lds_blocks = 512;    // single-workgroup path: slot groups x vectors
     int lds_radix = 8;       // single-workgroup path: largest FFT radix (8 or 16)
     int p3_blocks = 1024;    // inverse column pass: column tiles x slot groups x vectors
+    int p1_blocks = 0;       // forward column pass: column tiles x slot groups x vectors
+                             // (0: one workgroup per tile, slot and vector)
     int64_t nc = 0;  // complex lanes
     int64_t ncs = 0; // lane stride of the Cholesky columns, packed input and partial sums:
                      // nc rounded up to 128 bytes so that column tiles never straddle lines
@@ -273,7 +275,7 @@ double *symbol_spectrum64(thx_plan *p, hipStream_t s)
         launch_twiddles(twL1, nullptr, g.L1, g.L1, s);
         launch_twiddles(twL2, nullptr, g.L2, g.L2, s);
         launch_twiddles(twA, nullptr, L, g.L1, s);
-        if (!launch_mp_p1<double>(g, nullptr, 0, 0, nullptr, 0, 1, emb, U, 1, twL2, twA, s))
+        if (!launch_mp_p1<double>(g, nullptr, 0, 0, nullptr, 0, 1, 1, emb, U, 1, twL2, twA, s))
             throw HipFail{hipErrorInvalidValue};
         if (!launch_mp_p2<double>(g, U, 1, 1, nullptr, twL1, twA, twL2, false, perm, 1.0 / (double)L, s))
             throw HipFail{hipErrorInvalidValue};
@@ -456,6 +458,8 @@ void build_fft(thx_plan *p, hipStream_t s)
         int64_t row = 0;
         if (const char *e = getenv("THX_ROW_LEN")) row = atoll(e);
         p->geom = f64 ? multipass_geom<double>(L, row) : multipass_geom<float>(L, row);
+        // THX_P1_BLOCKS: forward-column-pass workgroups per launch before any tuning
+        if (const char *e = getenv("THX_P1_BLOCKS")) p->p1_blocks = std::max(0, atoi(e));
         const MultiPassGeom &g = p->geom;
         p->twL1 = make_twiddles(p, g.L1, g.L1, s, 0);
         p->twL2 = make_twiddles(p, g.L2, g.L2, s, 1);
@@ -827,6 +831,14 @@ void ensure_workspace(thx_plan *p, int64_t batch)
     p->ws_batch = batch;
 }
 
+// slots per forward-column-pass workgroup for `ns` slots of `batch` vectors
+int p1_slots_per_block(const thx_plan *p, int ns, int64_t batch)
+{
+    if (p->p1_blocks <= 0) return 1;
+    const int64_t items = p->geom.L1 / p->geom.TC * (int64_t)ns * batch;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(ns, items / p->p1_blocks));
+}
+
 template <typename T>
 void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
                  int64_t N, int64_t batch, int64_t ld, hipStream_t s)
@@ -854,7 +866,8 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
                 const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
                 {
                     PhaseTimer t(p, THX_PHASE_COL_FWD, s);
-                    if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, nullptr, p->U, batch, p->twL2, p->twA, s))
+                    if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch), nullptr,
+                                         p->U, batch, p->twL2, p->twA, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
                 {
@@ -1061,6 +1074,7 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
             if (p->L / row < 2 || p->L / row > 1024) continue;
             configure_rows(p, row, s);
             if (p->geom.L1 != row) continue;
+            p->p1_blocks = 0;
             for (int p3 : {512, 1024, 2048}) {
                 p->p3_blocks = p3;
                 const float t = time_launches(run, s);
@@ -1069,6 +1083,15 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
         }
         configure_rows(p, best_row, s);
         p->p3_blocks = best_p3;
+        // then the forward column pass: several slots per workgroup when that
+        // still leaves enough workgroups
+        int best_p1 = 0;
+        for (int p1 : {8192, 2048}) {
+            p->p1_blocks = p1;
+            const float t = time_launches(run, s);
+            if (t < tb) tb = t, best_p1 = p1;
+        }
+        p->p1_blocks = best_p1;
     }
 }
 
@@ -1386,6 +1409,7 @@ thx_status thx_plan_launch_shape(const thx_plan *p, int32_t *lds_blocks, int32_t
     return THX_OK;
 }
 int32_t thx_plan_lds_radix(const thx_plan *p) { return p ? p->lds_radix : -1; }
+int32_t thx_plan_p1_blocks(const thx_plan *p) { return p ? p->p1_blocks : -1; }
 
 int32_t thx_plan_partial_groups(const thx_plan *p, int64_t batch)
 {

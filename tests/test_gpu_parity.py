@@ -169,6 +169,22 @@ def test_leg2cheb_lds_radix(thx, N, prec, radix, monkeypatch):
     assert plan.path == 1 and plan.lds_radix == radix
 
 
+# several slots per forward-column-pass workgroup (THX_P1_BLOCKS is read at plan
+# creation): 1 puts every slot of a vector's tile in one workgroup, 100 leaves
+# ragged slot groups
+@pytest.mark.parametrize("p1", [1, 100])
+@pytest.mark.parametrize("N,prec,batch", [(20000, 0, 3), (150000, 0, 1), (40000, 1, 2), (9000, 0, 5)])
+def test_leg2cheb_p1_slot_groups(thx, N, prec, batch, p1, monkeypatch):
+    monkeypatch.setenv("THX_P1_BLOCKS", str(p1))
+    plan, alpha, got = _run(thx, thx.LEG2CHEB, N, prec, flags=thx.FLAG_FORCE_FFT, seed=N + p1, batch=batch)
+    assert plan.path == 2 and plan.p1_blocks == p1
+    bar = TOL64 if prec == 0 else TOL32
+    for i in range(batch):
+        err = _err(got[i], oracle.matvec("leg2cheb", alpha[i]), alpha[i])
+        print(f"  vector {i}: K={plan.rank} L={plan.fft_length} err={err:.3e}", flush=True)
+        assert err < bar
+
+
 @pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 511, 512])
 @pytest.mark.parametrize("dense", [True, False])
 def test_leg2cheb_direct(thx, N, dense):
