@@ -145,6 +145,12 @@ int32_t thx_plan_lds_radix(const thx_plan *plan);
  * slot and vector; a positive value lets each workgroup transform its tile for
  * several consecutive slots.  -1 for a null plan. */
 int32_t thx_plan_p1_blocks(const thx_plan *plan);
+/* 1 if the (first) stage's three-pass FFT runs its forward column pass inside
+ * the row pass (columns of 2 or 4 entries: each row's column DFT is a
+ * direct sum over the nonzero half of the zero-padded input, so no
+ * intermediate array is written before the row transforms), as chosen by
+ * thx_plan_autotune; 0 otherwise; -1 for a null plan. */
+int32_t thx_plan_fused_columns(const thx_plan *plan);
 /* Partial-sum groups the (first) stage uses for an execution of `batch` vectors
  * (the extra reads of the final D1 step); 0 for paths without them. */
 int32_t thx_plan_partial_groups(const thx_plan *plan, int64_t batch);

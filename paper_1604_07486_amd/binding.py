@@ -50,6 +50,7 @@ _sig("thx_plan_autotune", ctypes.c_int, _vp, _i64, _vp)
 _sig("thx_plan_launch_shape", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("thx_plan_lds_radix", _i32, _vp)
 _sig("thx_plan_p1_blocks", _i32, _vp)
+_sig("thx_plan_fused_columns", _i32, _vp)
 _sig("thx_plan_partial_groups", _i32, _vp, _i64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
@@ -148,6 +149,11 @@ class Plan:
     def p1_blocks(self) -> int:
         """Workgroups targeted per forward column pass (0: one per tile, slot and vector)."""
         return int(_lib.thx_plan_p1_blocks(self._h))
+
+    @property
+    def fused_columns(self) -> bool:
+        """True if the forward column pass runs inside the row pass (columns of 2 or 4)."""
+        return int(_lib.thx_plan_fused_columns(self._h)) == 1
 
     @property
     def lds_radix(self) -> int:

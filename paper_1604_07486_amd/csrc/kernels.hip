@@ -1449,6 +1449,43 @@ constexpr int RMAX_ROW = 16;
 template <typename T, int L1>
 constexpr int p2_threads() { return fft_threads(L1, 1, RMAX_ROW); }
 
+// Row k2 of the row pass, from the forward input layout in registers: DFT,
+// times the permuted symbol row, inverse DFT, conjugate twiddle, stored to `row`
+// (the same steps as the tail of k_mp_p2, for the fused pass).
+template <typename T, int L1>
+__device__ __forceinline__ void p2_row(cpx<T> *v, cpx<T> *lds, int k2, cpx<T> *__restrict__ row,
+                                       const cpx<T> *__restrict__ tp, const cpx<T> *__restrict__ twL1,
+                                       const cpx<T> *__restrict__ twA, const cpx<T> *__restrict__ twL2)
+{
+    constexpr int NT = p2_threads<T, L1>();
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW>;
+    F::forward(v, lds, twL1);
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) {
+        int k1, c;
+        F::out_pos(e, k1, c);
+        v[e] = cmul(v[e], tp[k1]);
+    }
+    F::inverse(v, lds, twL1);
+    // Conjugate twiddle w_L^{-a1 k2} with a1 = j_p + r L1/RF (j_p = threadIdx.x
+    // + NT p): a per-thread factor w_L^{j_p k2} times the workgroup-uniform
+    // w_L^{r k2 L1/RF}, so only one table pair per group is gathered.
+    constexpr int RF = F::R_FIRST, PG = F::E / RF;
+    cpx<T> bp[PG];
+#pragma unroll
+    for (int p = 0; p < PG; ++p) bp[p] = tw_L<T, L1>(twA, twL2, ((int)threadIdx.x + NT * p) * k2);
+#pragma unroll
+    for (int r = 0; r < RF; ++r) {
+        const cpx<T> sr = tw_L<T, L1>(twA, twL2, r * (L1 / RF) * k2);
+#pragma unroll
+        for (int p = 0; p < PG; ++p) {
+            const int a1 = (int)threadIdx.x + NT * p + r * (L1 / RF);
+            const cpx<T> t = r == 0 ? bp[p] : cmul(bp[p], sr);
+            st_stream(row + a1, cmulc(v[p * RF + r], t));
+        }
+    }
+}
+
 template <typename T, int L1>
 __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int L2, int nsb,
                                                                 const cpx<T> *__restrict__ that_perm,
@@ -1506,6 +1543,80 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int 
             st_stream(row + a1, cmulc(v[p * RF + r], t));
         }
     }
+}
+
+// Row pass with the forward column pass fused in, for short columns (L2 = 2 or
+// 4).  The input l~_s o X is zero at positions a >= n (<= L/2 + 1), i.e. at
+// column entries a2 > L2/2, and at a2 = L2/2 except a = L/2, so the column DFT
+// for row k2 is a direct sum of L2/2 terms (+ the one at L/2):
+//   Y[a1, k2] = w_L^{a1 k2} sum_{a2 < L2/2} x[a1 + L1 a2] w_{L2}^{a2 k2}
+//               (+ (-1)^k2 x[L/2] at a1 = 0).
+// The row's workgroup reads those inputs itself (the L2 rows of one slot and
+// vector run back to back on one XCD, so the reads after the first hit its L2)
+// and no intermediate array is written or read before the row transforms.
+// Every row reads all L2/2 nonzero column entries, so the reads grow with L2:
+// measured faster than the two passes it replaces at L2 = 2 (0.69 against
+// 0.93 ms for 339 vectors of degree 8182, FP64), about even at 4, and 40%
+// slower at 8, which is therefore not built.
+template <typename T, int L1, int L2>
+__global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2f(
+    const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
+    int nslots, cpx<T> *__restrict__ U, int64_t batch, const cpx<T> *__restrict__ that_perm,
+    const cpx<T> *__restrict__ twL1, const cpx<T> *__restrict__ twA, const cpx<T> *__restrict__ twL2)
+{
+    static_assert(L2 == 2 || L2 == 4, "short columns only");
+    constexpr int NT = p2_threads<T, L1>();
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW>;
+    constexpr int RF = F::R_FIRST, PG = F::E / RF;
+    constexpr int64_t L = (int64_t)L1 * L2;
+    __shared__ cpx<T> lds[F::LDS];
+    // (slot, vector) items padded to a multiple of 8 so that the L2 rows of an
+    // item share an XCD: block = xcd + 8 m, item = xcd + 8 (m / L2), row = m % L2
+    const int xcd = (int)(blockIdx.x & 7), m = (int)(blockIdx.x >> 3);
+    const int64_t item = xcd + 8 * (int64_t)(m / L2);
+    const int k2 = m % L2;
+    const int64_t nsb = (int64_t)nslots * batch;
+    if (item >= nsb) return;
+    const int sl = (int)(item / batch);
+    const int64_t b = item % batch;
+    const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
+    const cpx<T> *Xb = X + b * nc;
+    cpx<T> wk[L2 / 2];
+#pragma unroll
+    for (int a2 = 0; a2 < L2 / 2; ++a2) wk[a2] = twL2[(a2 * k2) & (L2 - 1)];
+    cpx<T> v[F::E];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) v[e] = cpx<T>{0, 0};
+#pragma unroll
+    for (int a2 = 0; a2 < L2 / 2; ++a2) {
+#pragma unroll
+        for (int e = 0; e < F::E; ++e) {
+            int a1, c;
+            F::in_pos(e, a1, c);
+            const int64_t a = a1 + (int64_t)L1 * a2;
+            if (a < n) {
+                const cpx<T> x = cdiag(es[a], Xb[a]);
+                v[e] = a2 == 0 ? x : cadd(v[e], cmul(x, wk[a2]));
+            }
+        }
+    }
+    // the input at a = L/2 (column entry L2/2 of column 0: slot 0 of thread 0)
+    if (threadIdx.x == 0 && L / 2 < n) {
+        const cpx<T> x = cdiag(es[L / 2], Xb[L / 2]);
+        v[0] = (k2 & 1) ? csub(v[0], x) : cadd(v[0], x);
+    }
+    // twiddle w_L^{a1 k2}, a1 = j_p + r L1/RF, factored as in the epilogue
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+        const cpx<T> bp = tw_L<T, L1>(twA, twL2, ((int)threadIdx.x + NT * p) * k2);
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const cpx<T> t = r == 0 ? bp : cmul(bp, tw_L<T, L1>(twA, twL2, r * (L1 / RF) * k2));
+            v[p * RF + r] = cmul(v[p * RF + r], t);
+        }
+    }
+    cpx<T> *row = U + ((int64_t)sl * batch + b) * L + (int64_t)k2 * L1;
+    p2_row<T, L1>(v, lds, k2, row, that_perm + (int64_t)k2 * L1, twL1, twA, twL2);
 }
 
 template <typename T, int L1, int L2>
@@ -1661,6 +1772,43 @@ bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, co
 }
 template bool launch_mp_p2<double>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
 template bool launch_mp_p2<float>(const MultiPassGeom &, void *, int, int64_t, const void *, const void *, const void *, const void *, bool, void *, double, hipStream_t);
+
+template <typename T, int L1>
+bool mp_p2f_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
+               int nslots, void *U, int64_t batch, const void *that_perm, const void *twL1, const void *twA,
+               const void *twL2, hipStream_t s)
+{
+    const int64_t items = ((int64_t)nslots * batch + 7) / 8 * 8;
+    switch (g.L2) {
+#define THX_P2F(LL2)                                                                                     \
+    case LL2:                                                                                            \
+        k_mp_p2f<T, L1, LL2><<<dim3((unsigned)(items * LL2)), p2_threads<T, L1>(), 0, s>>>(             \
+            (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, slot0, nslots, (cpx<T> *)U, batch,            \
+            (const cpx<T> *)that_perm, (const cpx<T> *)twL1, (const cpx<T> *)twA, (const cpx<T> *)twL2); \
+        return true;
+        THX_P2F(2) THX_P2F(4)
+#undef THX_P2F
+    default: return false;
+    }
+}
+
+template <typename T>
+bool launch_mp_p2f(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
+                   int nslots, void *U, int64_t batch, const void *that_perm, const void *twL1, const void *twA,
+                   const void *twL2, hipStream_t s)
+{
+    if (n > g.L1 * g.L2 / 2 + 1 || n > nc || nslots < 1) return false; // zero padding above L/2 is assumed
+    if ((int64_t)nslots * batch * g.L2 + 8 * g.L2 > ((int64_t)1 << 31) - 1) return false;
+    if (g.L1 == mp_row_short<T>())
+        return mp_p2f_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, U, batch, that_perm, twL1,
+                                                     twA, twL2, s);
+    if (g.L1 == mp_row_long<T>())
+        return mp_p2f_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, U, batch, that_perm, twL1,
+                                                    twA, twL2, s);
+    return false;
+}
+template bool launch_mp_p2f<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, void *, int64_t, const void *, const void *, const void *, const void *, hipStream_t);
+template bool launch_mp_p2f<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, void *, int64_t, const void *, const void *, const void *, const void *, hipStream_t);
 
 template <typename T, int L1>
 bool mp_p3_l2(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell, int slot0,

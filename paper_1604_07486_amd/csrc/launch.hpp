@@ -187,6 +187,12 @@ template <typename T>
 bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,
                   const void *twL1, const void *twA, const void *twL2, bool full, void *out,
                   double scale, hipStream_t s);
+// P1 and P2 fused for columns of 2 or 4 (false for other geometries): each row
+// workgroup forms its row's column DFT directly from ell_s o X, then as P2
+template <typename T>
+bool launch_mp_p2f(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
+                   int nslots, void *U, int64_t batch, const void *that_perm, const void *twL1, const void *twA,
+                   const void *twL2, hipStream_t s);
 // P3: inverse column FFTs, scaled by ell_s and summed over the slots of group g
 template <typename T>
 bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, const void *ell,

@@ -144,6 +144,7 @@ struct thx_plan {
     int p3_blocks = 1024;    // inverse column pass: column tiles x slot groups x vectors
     int p1_blocks = 0;       // forward column pass: column tiles x slot groups x vectors
                              // (0: one workgroup per tile, slot and vector)
+    bool fuse_p1 = false;    // columns of 2 or 4: forward column pass fused into the row pass
     int64_t nc = 0;  // complex lanes
     int64_t ncs = 0; // lane stride of the Cholesky columns, packed input and partial sums:
                      // nc rounded up to 128 bytes so that column tiles never straddle lines
@@ -459,7 +460,11 @@ void build_fft(thx_plan *p, hipStream_t s)
         if (const char *e = getenv("THX_ROW_LEN")) row = atoll(e);
         p->geom = f64 ? multipass_geom<double>(L, row) : multipass_geom<float>(L, row);
         // THX_P1_BLOCKS: forward-column-pass workgroups per launch before any tuning
-        if (const char *e = getenv("THX_P1_BLOCKS")) p->p1_blocks = std::max(0, atoi(e));
+        // (-1: fused into the row pass where the columns allow it)
+        if (const char *e = getenv("THX_P1_BLOCKS")) {
+            p->p1_blocks = std::max(0, atoi(e));
+            p->fuse_p1 = atoi(e) < 0;
+        }
         const MultiPassGeom &g = p->geom;
         p->twL1 = make_twiddles(p, g.L1, g.L1, s, 0);
         p->twL2 = make_twiddles(p, g.L2, g.L2, s, 1);
@@ -820,9 +825,11 @@ void ensure_workspace(thx_plan *p, int64_t batch)
     p->row0 = dalloc<double>(batch);
     if (p->row0_direct) p->row0_part = dalloc<double>(batch * ROW0_PMAX);
     if (p->path == 2) {
-        // slot chunk so that the FFT intermediates stay within ~2 GiB
+        // slot chunk so that the FFT intermediates stay within ~8 GiB (of the
+        // 288 GB of HBM): fewer chunks mean fewer launches and fewer partial-sum
+        // groups for the final step to read
         const int64_t per = (int64_t)es * p->L * batch;
-        int64_t sc = std::max<int64_t>(1, ((int64_t)2 << 30) / per);
+        int64_t sc = std::max<int64_t>(1, ((int64_t)8 << 30) / per);
         if (const char *e = getenv("THX_SLOT_CHUNK")) sc = std::max<int64_t>(1, std::min<int64_t>(sc, atoll(e)));
         sc = std::min<int64_t>(sc, std::max(1, p->S));
         p->U_slots = sc;
@@ -864,13 +871,18 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
             const int64_t tiles = g.L1 / g.TC;
             for (int s0 = 0; s0 < p->S; s0 += (int)p->U_slots) {
                 const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
-                {
-                    PhaseTimer t(p, THX_PHASE_COL_FWD, s);
-                    if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch), nullptr,
-                                         p->U, batch, p->twL2, p->twA, s))
+                if (p->fuse_p1 && g.L2 <= 4) {
+                    PhaseTimer t(p, THX_PHASE_ROW, s);
+                    if (!launch_mp_p2f<T>(g, p->X, p->ncs, n, ell, s0, ns, p->U, batch, p->that, p->twL1, p->twA,
+                                          p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
-                }
-                {
+                } else {
+                    {
+                        PhaseTimer t(p, THX_PHASE_COL_FWD, s);
+                        if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch),
+                                             nullptr, p->U, batch, p->twL2, p->twA, s))
+                            throw HipFail{hipErrorInvalidValue};
+                    }
                     PhaseTimer t(p, THX_PHASE_ROW, s);
                     if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
                         throw HipFail{hipErrorInvalidValue};
@@ -1070,26 +1082,33 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
         int64_t best_row = p->geom.L1;
         int best_p3 = p->p3_blocks;
         float tb = 1e30f;
+        bool best_fuse = false;
         for (int64_t row : rows) {
             if (p->L / row < 2 || p->L / row > 1024) continue;
             configure_rows(p, row, s);
             if (p->geom.L1 != row) continue;
             p->p1_blocks = 0;
-            for (int p3 : {512, 1024, 2048}) {
-                p->p3_blocks = p3;
-                const float t = time_launches(run, s);
-                if (t < tb) tb = t, best_row = row, best_p3 = p3;
+            for (int fuse = 0; fuse < (p->geom.L2 <= 4 ? 2 : 1); ++fuse) {
+                p->fuse_p1 = fuse != 0;
+                for (int p3 : {512, 1024, 2048}) {
+                    p->p3_blocks = p3;
+                    const float t = time_launches(run, s);
+                    if (t < tb) tb = t, best_row = row, best_p3 = p3, best_fuse = p->fuse_p1;
+                }
             }
         }
         configure_rows(p, best_row, s);
         p->p3_blocks = best_p3;
-        // then the forward column pass: several slots per workgroup when that
-        // still leaves enough workgroups
+        p->fuse_p1 = best_fuse;
+        // then the separate forward column pass: several slots per workgroup when
+        // that still leaves enough workgroups
         int best_p1 = 0;
-        for (int p1 : {8192, 2048}) {
-            p->p1_blocks = p1;
-            const float t = time_launches(run, s);
-            if (t < tb) tb = t, best_p1 = p1;
+        if (!p->fuse_p1) {
+            for (int p1 : {8192, 2048}) {
+                p->p1_blocks = p1;
+                const float t = time_launches(run, s);
+                if (t < tb) tb = t, best_p1 = p1;
+            }
         }
         p->p1_blocks = best_p1;
     }
@@ -1410,6 +1429,11 @@ thx_status thx_plan_launch_shape(const thx_plan *p, int32_t *lds_blocks, int32_t
 }
 int32_t thx_plan_lds_radix(const thx_plan *p) { return p ? p->lds_radix : -1; }
 int32_t thx_plan_p1_blocks(const thx_plan *p) { return p ? p->p1_blocks : -1; }
+int32_t thx_plan_fused_columns(const thx_plan *p)
+{
+    if (!p) return -1;
+    return (p->path == 2 && !p->dense && p->fuse_p1 && p->geom.L2 <= 4) ? 1 : 0;
+}
 
 int32_t thx_plan_partial_groups(const thx_plan *p, int64_t batch)
 {

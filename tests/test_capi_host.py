@@ -117,6 +117,9 @@ def test_introspection_null_plan(lib):
     lib.thx_plan_p1_blocks.restype = ctypes.c_int32
     lib.thx_plan_p1_blocks.argtypes = [ctypes.c_void_p]
     assert lib.thx_plan_p1_blocks(None) == -1
+    lib.thx_plan_fused_columns.restype = ctypes.c_int32
+    lib.thx_plan_fused_columns.argtypes = [ctypes.c_void_p]
+    assert lib.thx_plan_fused_columns(None) == -1
     lib.thx_plan_enable_timing.restype = ctypes.c_int
     lib.thx_plan_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     assert lib.thx_plan_enable_timing(None, 0xFFFFFFFF) == 1

@@ -185,6 +185,43 @@ def test_leg2cheb_p1_slot_groups(thx, N, prec, batch, p1, monkeypatch):
         assert err < bar
 
 
+# forward column pass fused into the row pass (columns of 2 or 4 entries;
+# THX_P1_BLOCKS = -1 asks for it at plan creation): both row lengths, both
+# precisions, the extra input at L/2 (N = L), batches not a multiple of 8
+@pytest.mark.parametrize("N,prec,row,batch", [
+    (8192, 0, 2048, 3), (5000, 0, 2048, 1), (6000, 0, 2048, 9),                          # columns of 4
+    (8192, 0, 4096, 2), (5000, 0, 4096, 1), (16383, 0, 4096, 1), (16384, 0, 4096, 11),   # 2, 2, 4, 4
+    (16384, 1, 4096, 3), (10000, 1, 8192, 5), (32768, 1, 8192, 1), (24000, 1, 8192, 2),  # 4, 2, 4, 4
+])
+def test_leg2cheb_fused_columns(thx, N, prec, row, batch, monkeypatch):
+    monkeypatch.setenv("THX_P1_BLOCKS", "-1")
+    monkeypatch.setenv("THX_ROW_LEN", str(row))
+    plan, alpha, got = _run(thx, thx.LEG2CHEB, N, prec, flags=thx.FLAG_FORCE_FFT, seed=N + row, batch=batch)
+    assert plan.path == 2 and plan.fused_columns
+    bar = TOL64 if prec == 0 else TOL32
+    for i in range(batch):
+        if N > 20000:
+            rows = inputs.sample_rows(N, 256, seed=i)
+            ref = oracle.matvec("leg2cheb", alpha[i], rows=rows)
+            err = float(np.max(np.abs(got[i][rows] - ref)) / np.sum(np.abs(alpha[i])))
+        else:
+            err = _err(got[i], oracle.matvec("leg2cheb", alpha[i]), alpha[i])
+        print(f"  vector {i}: K={plan.rank} L={plan.fft_length} err={err:.3e}", flush=True)
+        assert err < bar
+
+
+@pytest.mark.parametrize("kind,params,N", [
+    (4, (0.5, -0.25), 3000),          # Laguerre: no parity split, two ranks per complex slot
+    (1, (), 9000),                    # cheb2leg: row 0 computed directly
+])
+def test_fused_columns_other_kinds(thx, kind, params, N, monkeypatch):
+    monkeypatch.setenv("THX_P1_BLOCKS", "-1")
+    monkeypatch.setenv("THX_ROW_LEN", "4096")
+    plan, _ = _check_full(thx, kind, N, thx.FP64, params, flags=thx.FLAG_FORCE_FFT, seed=N,
+                          tol=1e-17 if kind == 1 else None, p=1.5 if kind == 1 else 1.0)
+    assert plan.path == 2 and plan.fused_columns
+
+
 @pytest.mark.parametrize("N", [0, 1, 2, 7, 300, 511, 512])
 @pytest.mark.parametrize("dense", [True, False])
 def test_leg2cheb_direct(thx, N, dense):
