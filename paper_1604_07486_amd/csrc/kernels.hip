@@ -268,27 +268,53 @@ __global__ __launch_bounds__(1024) void k_pchol_select(PcholArgs a, int r)
     }
 }
 
+// Column r of every active part.  The earlier columns are read once per 16-byte
+// lane: for two parts, component q of slot m is column m of part q, so one
+// pass updates both; for one part, the two components of slot m are its
+// columns 2m and 2m + 1.
 __global__ __launch_bounds__(PC_NT) void k_pchol_column(PcholArgs a, int r)
 {
     __shared__ double sv[PC_NT];
     __shared__ int si[PC_NT];
     const PcholState *st = a.st;
     const int64_t i = (int64_t)blockIdx.x * PC_NT + threadIdx.x;
-    for (int q = 0; q < a.parts; ++q) {
-        if (!st->active[q]) continue; // uniform across the grid
-        const int p = st->cur_p[q];
-        const double sq = sqrt(st->cur_piv[q]);
+    const cpx<double> *ec = reinterpret_cast<const cpx<double> *>(a.ell);
+    bool act[2], in[2];
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        act[q] = q < a.parts && st->active[q] != 0; // uniform across the grid
+        in[q] = act[q] && i < a.nc && i >= a.a0[q] && i < a.n[q];
+        if (in[q]) acc[q] = a.hk[i + st->cur_p[q] + hk_offset(a, q)];
+    }
+    if (a.parts == 2) {
+        if (in[0] || in[1]) {
+            const double *R0 = st->R[0][r], *R1 = st->R[1][r];
+            for (int m = 0; m < r; ++m) {
+                const cpx<double> e = ec[(int64_t)m * a.nc + i];
+                acc[0] = fma(-e.x, R0[m], acc[0]);
+                acc[1] = fma(-e.y, R1[m], acc[1]);
+            }
+        }
+    } else if (in[0]) {
+        const double *R0 = st->R[0][r];
+        for (int m = 0; 2 * m < r; ++m) {
+            const cpx<double> e = ec[(int64_t)m * a.nc + i];
+            acc[0] = fma(-e.x, R0[2 * m], acc[0]);
+            if (2 * m + 1 < r) acc[0] = fma(-e.y, R0[2 * m + 1], acc[0]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (!act[q]) continue;
         double dn = 0.0;
         if (i < a.nc) {
             dn = a.d[q * a.nc + i];
-            if (i >= a.a0[q] && i < a.n[q]) {
-                double acc = a.hk[i + p + hk_offset(a, q)];
-                const double *Rr = st->R[q][r];
-                for (int m = 0; m < r; ++m) acc = fma(-a.ell[ell_index(a.parts, q, m, i, a.nc)], Rr[m], acc);
-                const double lt = acc / sq;
+            if (in[q]) {
+                const double lt = acc[q] / sqrt(st->cur_piv[q]);
                 a.ell[ell_index(a.parts, q, r, i, a.nc)] = lt;
                 dn = fma(-lt, lt, dn);
-                if (!(dn > 0.0) || i == p) dn = 0.0;
+                if (!(dn > 0.0) || i == st->cur_p[q]) dn = 0.0;
                 a.d[q * a.nc + i] = dn;
             }
         }
