@@ -702,21 +702,43 @@ __device__ __forceinline__ Pair sc_lane(const KindDesc &k, const double *al, int
     return Pair{q <= N ? d2_of(k, q) * al[q] : 0.0, 0.0};
 }
 
+// Sums in a fixed order (deterministic): within a wave by butterfly shuffles,
+// across the SC_NT / 64 waves through LDS.
+constexpr int SC_NW = SC_NT / 64;
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// sum of v over the lanes >= this lane of the wave
+__device__ __forceinline__ double wave_suffix(double v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_down(v, o, 64);
+        if (lane + o < 64) v += u;
+    }
+    return v;
+}
 __device__ __forceinline__ void block_sum2(double &x, double &y, double *sx, double *sy)
 {
-    const int t = threadIdx.x;
-    sx[t] = x;
-    sy[t] = y;
-    __syncthreads();
-    for (int h = SC_NT / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            sx[t] += sx[t + h];
-            sy[t] += sy[t + h];
-        }
-        __syncthreads();
+    x = wave_sum(x);
+    y = wave_sum(y);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sx[w] = x;
+        sy[w] = y;
     }
-    x = sx[0];
-    y = sy[0];
+    __syncthreads();
+    x = 0.0;
+    y = 0.0;
+#pragma unroll
+    for (int i = 0; i < SC_NW; ++i) {
+        x += sx[i];
+        y += sy[i];
+    }
     __syncthreads();
 }
 
@@ -726,7 +748,7 @@ __device__ __forceinline__ void block_sum2(double &x, double &y, double *sx, dou
 __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
                                                       int64_t N0, double *tot, int nchunk)
 {
-    __shared__ double sx[SC_NT], sy[SC_NT];
+    __shared__ double sx[SC_NW], sy[SC_NW];
     const int c = blockIdx.x;
     const int64_t b = blockIdx.y;
     int64_t base, N;
@@ -756,7 +778,7 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
 {
     constexpr int LP = SC_CH + SC_CH / 32;
     __shared__ double lx[LP], ly[LP];
-    __shared__ double sx[SC_NT], sy[SC_NT];
+    __shared__ double sx[SC_NW], sy[SC_NW];
     const int c = blockIdx.x;
     const int64_t b = blockIdx.y;
     int64_t base, N;
@@ -764,7 +786,7 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
     const int64_t nl = k.parity ? N / 2 + 1 : N + 1; // lanes of this vector
     if ((int64_t)c * SC_CH >= nl) return;            // uniform over the block
     const double *al = alpha + base;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t q0 = (int64_t)c * SC_CH;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
@@ -789,18 +811,22 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
         vx[i] = rx;
         vy[i] = ry;
     }
-    // exclusive reverse scan of the run totals (Hillis-Steele over the block)
-    sx[t] = rx;
-    sy[t] = ry;
-    __syncthreads();
-    for (int h = 1; h < SC_NT; h <<= 1) {
-        const double ax = t + h < SC_NT ? sx[t + h] : 0.0, ay = t + h < SC_NT ? sy[t + h] : 0.0;
-        __syncthreads();
-        sx[t] += ax;
-        sy[t] += ay;
-        __syncthreads();
+    // exclusive reverse scan of the run totals: within the wave by shuffles,
+    // then the totals of the later waves
+    const double ix = wave_suffix(rx), iy = wave_suffix(ry);
+    double ex = __shfl_down(ix, 1, 64), ey = __shfl_down(iy, 1, 64);
+    if (lane == 63) ex = ey = 0.0;
+    if (lane == 0) {
+        sx[w] = ix;
+        sy[w] = iy;
     }
-    const double ex = (t + 1 < SC_NT ? sx[t + 1] : 0.0) + cx, ey = (t + 1 < SC_NT ? sy[t + 1] : 0.0) + cy;
+    __syncthreads();
+    for (int w2 = w + 1; w2 < SC_NW; ++w2) {
+        ex += sx[w2];
+        ey += sy[w2];
+    }
+    ex += cx;
+    ey += cy;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
         lx[sc_pad(t * SC_PER + i)] = vx[i] + ex;
