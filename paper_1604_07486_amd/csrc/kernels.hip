@@ -472,11 +472,51 @@ template void launch_pack<float>(const KindDesc &, const int64_t *, const int64_
 // (2a, 2a + 1) of lane a, the others output a (the sum of its two packed
 // ranks).  The G partial results are loaded four at a time and added in
 // group order.
+// The alias term only arises for n - 1 = L/2, so its factor is a plan constant:
+// alias[q] = sum_s l~_s[L/2].q l~_s[0].q for the two parts of the parity kinds,
+// alias[0] = sum_s (both packed ranks of slot s) otherwise, summed in slot order.
+__global__ __launch_bounds__(KMAX) void k_alias_sums(const double *ell64, int64_t nc_ell, int S, int parts,
+                                                     int64_t idx, double *alias)
+{
+    __shared__ double pr[2][KMAX];
+    const int s = threadIdx.x;
+    if (s < S) {
+        const double *e = ell64 + 2 * ((int64_t)s * nc_ell + idx), *o = ell64 + 2 * ((int64_t)s * nc_ell);
+        pr[0][s] = e[0] * o[0];
+        pr[1][s] = e[1] * o[1];
+    }
+    __syncthreads();
+    if (s == 0) {
+        double g0 = 0.0, g1 = 0.0;
+        for (int t = 0; t < S; ++t) {
+            if (parts == 2) {
+                g0 += pr[0][t];
+                g1 += pr[1][t];
+            } else {
+                g0 += pr[0][t];
+                g0 += pr[1][t];
+            }
+        }
+        alias[0] = g0;
+        alias[1] = g1;
+    }
+}
+
+void launch_alias_sums(const double *ell64, int64_t nc_ell, int S, int parts, int64_t L, double *alias,
+                       hipStream_t s)
+{
+    if (S < 1 || S > KMAX || L / 2 >= nc_ell) {
+        launch_zero(alias, 2 * (int64_t)sizeof(double), s); // the alias position is never an output
+        return;
+    }
+    k_alias_sums<<<1, KMAX, 0, s>>>(ell64, nc_ell, S, parts, L / 2, alias);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
                                                 double *beta, int64_t N0, const cpx<T> *W, int G, int64_t nc,
-                                                int64_t batch, int64_t L, const double *ell64, int64_t nc_ell,
-                                                int S, const double *tsym, const double *row0)
+                                                int64_t batch, int64_t L, const double *alias,
+                                                const double *tsym, const double *row0)
 {
     const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t b = blockIdx.y;
@@ -512,12 +552,7 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
             if (j > N) break;
             double w = q ? wy : wx;
             const int64_t nq = q ? (N + 1) / 2 : N / 2 + 1;
-            if (2 * nq - 2 == L && a == nq - 1) {
-                double gs = 0.0;
-                for (int s = 0; s < S; ++s)
-                    gs = fma(ell64[2 * ((int64_t)s * nc_ell + nq - 1) + q], ell64[2 * ((int64_t)s * nc_ell) + q], gs);
-                w -= tsym[nq - 1] * gs * (d2_of(k, q) * al[q]);
-            }
+            if (2 * nq - 2 == L && a == nq - 1) w -= tsym[nq - 1] * alias[q] * (d2_of(k, q) * al[q]);
             double out = d1_of(k, j) * w;
             if (row0 && j == 0) out = row0[b];
             beta[base + j] = out;
@@ -525,15 +560,7 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
     } else {
         const int64_t j = a, n = N + 1;
         double w = wsum;
-        if (2 * n - 2 == L && j == n - 1) {
-            double gs = 0.0;
-            for (int s = 0; s < S; ++s) {
-                const int64_t e = 2 * ((int64_t)s * nc_ell + n - 1), o = 2 * ((int64_t)s * nc_ell);
-                gs = fma(ell64[e], ell64[o], gs);
-                gs = fma(ell64[e + 1], ell64[o + 1], gs);
-            }
-            w -= tsym[n - 1] * gs * (d2_of(k, 0) * al[0]);
-        }
+        if (2 * n - 2 == L && j == n - 1) w -= tsym[n - 1] * alias[0] * (d2_of(k, 0) * al[0]);
         double out = d1_of(k, j) * w;
         if (row0 && j == 0) out = row0[b];
         beta[base + j] = out;
@@ -543,17 +570,17 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
 template <typename T>
 void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                    int64_t ld, double *beta, int64_t N, int64_t batch, const void *Wpart, int G,
-                   int64_t nc, int64_t L, const double *ell64, int64_t nc_ell, int S,
-                   const double *tsym, const double *row0, hipStream_t s)
+                   int64_t nc, int64_t L, const double *alias, const double *tsym, const double *row0,
+                   hipStream_t s)
 {
     const int nt = 256;
     const int64_t lanes = k.parity ? N / 2 + 1 : N + 1;
     dim3 grid((unsigned)((lanes + nt - 1) / nt), (unsigned)batch);
     k_unpack<T><<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, (const cpx<T> *)Wpart, G,
-                                    nc, batch, L, ell64, nc_ell, S, tsym, row0);
+                                    nc, batch, L, alias, tsym, row0);
 }
-template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
-template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, int64_t, int, const double *, const double *, hipStream_t);
+template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
+template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
 
 // Row 0 computed directly when the Hankel part is PSD only on indices >= 1
 // (cheb2leg, Sec. 5.1; Jacobi case 3, Sec. 5.3): rows/columns >= 1 go through

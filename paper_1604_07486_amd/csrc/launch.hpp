@@ -102,8 +102,12 @@ template <typename T>
 void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                    int64_t ld, double *beta, int64_t N, int64_t batch,
                    const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc, int64_t L,
-                   const double *ell64, int64_t nc_ell, int S, const double *tsym,
+                   const double *alias /*launch_alias_sums*/, const double *tsym,
                    const double *row0, hipStream_t s);
+// the two plan constants of the circulant alias correction at n - 1 = L/2, from the
+// normalised Cholesky columns (zeros when L/2 is not a lane of the plan)
+void launch_alias_sums(const double *ell64, int64_t nc_ell, int S, int parts, int64_t L, double *alias,
+                       hipStream_t s);
 // row 0 by a direct dot product: partial sums over up to ROW0_PMAX workgroups per
 // vector into part[batch][ROW0_PMAX], then summed in a fixed order into row0[batch]
 constexpr int ROW0_PMAX = 256;

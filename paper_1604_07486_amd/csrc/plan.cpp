@@ -164,6 +164,7 @@ struct thx_plan {
     double *d1tab = nullptr, *d2tab = nullptr;
     double *ell64 = nullptr;
     float *ell32 = nullptr;
+    double *alias = nullptr; // [2] plan constants of the circulant alias correction
     void *that = nullptr;     // symbol spectrum in working precision (natural or permuted)
     void *twL = nullptr;      // LDS path: w_L^k, k < L
     void *twL1 = nullptr, *twL2 = nullptr, *twA = nullptr; // three-pass tables
@@ -195,6 +196,7 @@ struct thx_plan {
         dfree(d2tab);
         dfree(ell64);
         dfree(ell32);
+        dfree(alias);
         dfree(that);
         if (prec == THX_FP64) {
             dfree(twL);
@@ -431,6 +433,9 @@ void build_fft(thx_plan *p, hipStream_t s)
     p->L = std::max<int64_t>(64, next_pow2(2 * p->nc - 2));
     if (p->L > ((int64_t)1 << 22)) throw std::invalid_argument("L");
     run_pchol(p, s);
+    p->alias = dalloc<double>(2);
+    launch_alias_sums(p->ell64, p->ncs, p->S, p->parts, p->L, p->alias, s);
+    launch_check();
     const bool f64 = p->prec == THX_FP64;
     if (!f64) {
         p->ell32 = dalloc<float>(2 * (int64_t)std::max(p->S, 1) * p->ncs);
@@ -911,8 +916,8 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
     }
     {
         PhaseTimer t(p, THX_PHASE_UNPACK, s);
-        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->ncs, p->L, p->ell64, p->ncs,
-                         p->S, p->tsym, row0, s);
+        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->ncs, p->L, p->alias, p->tsym,
+                         row0, s);
     }
     launch_check();
 }
