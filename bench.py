@@ -65,6 +65,36 @@ TRAFFIC_SOURCES = ["paper_1604_07486_amd/csrc/kernels.hip", "paper_1604_07486_am
                    "paper_1604_07486_amd/csrc/plan.cpp"]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_extras(oracle, inputs, alpha, N, threads):
+    """Single-thread rate on a bounded sample of rows at the headline size, and full O(N^2)
+    conversions at small N with all threads (a few seconds of CPU in total)."""
+    g = inputs.rng(98)
+    r = g.integers(0, N + 1, size=256)
+    t0 = time.perf_counter()
+    oracle.matvec("leg2cheb", alpha, rows=r, nthreads=1)
+    t1 = time.perf_counter() - t0
+    full = []
+    for n in (2048, 4096, 65536):
+        a = inputs.coeffs(n, 1.0, seed=n)
+        t0 = time.perf_counter()
+        oracle.matvec("leg2cheb", a, nthreads=threads)
+        dt = time.perf_counter() - t0
+        full.append({"N": n, "seconds": round(dt, 4), "coeffs_per_s": round((n + 1) / dt, 1)})
+    return {"single_thread": {"value": round(256 / t1, 2), "unit": "coeffs/s", "cores": 1,
+                              "sample": "256 random output rows of leg2cheb at N=2^20"},
+            "full_conversions": full, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
 def source_digest():
     import hashlib
     h = hashlib.sha256()
@@ -446,6 +476,7 @@ def main():
                "sample": f"{done_rows} uniformly random output rows of leg2cheb at N=2^20 "
                          f"(O(N) each, extended precision) in {t_used:.1f} s; a full conversion "
                          f"would take (N+1)/value = {(N + 1) / rows_per_s:.0f} s (extrapolated)"}
+        cpu.update(oracle_extras(oracle, inputs, alpha, N, threads))
 
     out = {
         "metric": METRIC,
