@@ -131,13 +131,13 @@ def write_traffic(fetch_db, write_db):
         "# HBM traffic of the row pass (k_mp_p2<double, 2048>), leg2cheb N=2^20 FP64 headline plan",
         "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
         "# execute dispatches; factors = bytes of the 512 MiB device copy in the same run / counter.",
-        "# Commands (repo root $R, from /tmp with TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc/fp64_FETCH_SIZE -o pmc -- python3 $R/bench.py "
+        "# Commands (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/fp64_FETCH_SIZE -o pmc -- python3 $R/bench.py "
         "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
-        "#   rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc/fp64_WRITE_SIZE -o pmc -- python3 $R/bench.py "
+        "#   rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/fp64_WRITE_SIZE -o pmc -- python3 $R/bench.py "
         "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
-        "#   python3 bench.py --write-traffic gpurun_out/pmc/fp64_FETCH_SIZE/pmc_results.db "
-        "gpurun_out/pmc/fp64_WRITE_SIZE/pmc_results.db",
+        "#   python3 bench.py --write-traffic $OUT/pmc/fp64_FETCH_SIZE/pmc_results.db "
+        "$OUT/pmc/fp64_WRITE_SIZE/pmc_results.db",
         f"kernel = {TRAFFIC_KERNEL}",
         "phase = row",
         f"fetch_kib_per_dispatch = {out['fetch'][0]:.1f}",
