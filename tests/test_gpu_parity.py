@@ -463,6 +463,38 @@ def test_batch_graph_replays_match_eager(thx):
         (junk * 2.0).sum().item()
 
 
+# the fused column pass (columns of 2 or 4) and slot-grouped forward passes inside
+# a captured batch: replays bitwise equal to the eager run, and parity on
+# members of every bucket
+@pytest.mark.parametrize("p1,row", [("-1", "4096"), ("1", "2048"), ("100", "4096")])
+def test_batch_graph_fused_and_grouped_passes(thx, p1, row, monkeypatch):
+    import torch
+    monkeypatch.setenv("THX_P1_BLOCKS", p1)
+    monkeypatch.setenv("THX_ROW_LEN", row)
+    degrees = np.concatenate([inputs.batch_degrees(40, 4100, 20000, seed=61), [8192, 16383]]).astype(np.int64)
+    print(f"[case] batch graph THX_P1_BLOCKS={p1} THX_ROW_LEN={row} members={len(degrees)}", flush=True)
+    flat, parts = _batch_inputs(degrees, 1.0, 11)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64, thx.FP64)
+    a = _dev(flat)
+    eager = torch.empty_like(a)
+    bt.execute(a, eager)
+    torch.cuda.synchronize()
+    out = torch.empty_like(a)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        bt.execute(a, out, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        junk = torch.randn(1 << 20, device="cuda:0", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+    got = out.cpu().numpy()
+    for i in list(range(0, len(degrees), 7)) + [len(degrees) - 2, len(degrees) - 1]:
+        al = parts[i]
+        o = int(bt.offsets[i])
+        err = _err(got[o:o + len(al)], oracle.matvec("leg2cheb", al), al)
+        assert err < TOL64, (i, err)
+
+
 @pytest.mark.parametrize("kind,params", [(2, (1.5, 0.5)), (5, (0.5, -0.25)), (2, (3.25, 0.5))])
 def test_batch_config5_kinds(thx, kind, params):
     """Many short vectors (dense bucket) plus a few long ones (FFT or unit-step buckets) in one CSR
