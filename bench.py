@@ -41,7 +41,7 @@ def parse():
                     help="run only the headline timed loop (for profiler runs)")
     ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
-    ap.add_argument("--only", choices=["batched", "config5"], default=None,
+    ap.add_argument("--only", choices=["batched", "config5", "sweep"], default=None,
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
@@ -249,6 +249,33 @@ def sampled_error(oracle, kind, alpha, got, rows):
     return float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
 
 
+def run_sweep(thx, torch, inputs, oracle, dev, steps):
+    """Precision sweep of Legendre -> Chebyshev: FP64 (Hankel tol 1e-15) against FP32-bulk (1e-7)
+    at N = 2^12, 2^16, 2^20, 2^22 for coefficients decaying like (k+1)^-2 and undecayed; error
+    against the oracle on every row up to 2^16, on 256 sampled rows (+ the special ones) above."""
+    out = []
+    for lg in (12, 16, 20, 22):
+        N = 1 << lg
+        for p in (2.0, 0.0):
+            alpha = inputs.coeffs(N, p, seed=300 + lg)
+            a = torch.from_numpy(alpha).to(dev)
+            b = torch.empty_like(a)
+            rows = None if lg <= 16 else inputs.sample_rows(N, 256, seed=lg)
+            ref = oracle.matvec("leg2cheb", alpha, rows=rows)
+            for prec, tol, name in ((thx.FP64, 1e-15, "fp64"), (thx.FP32_BULK, 1e-7, "fp32_bulk")):
+                plan = thx.Plan(thx.LEG2CHEB, N, tol, prec)
+                plan.autotune(1)
+                n_steps = max(5, steps // (1 if lg <= 20 else 4))
+                ms, _ = time_plan(thx, torch, plan, a, b, n_steps, 3)
+                got = b.cpu().numpy()
+                err = float(np.max(np.abs((got if rows is None else got[rows]) - ref)) / np.sum(np.abs(alpha)))
+                out.append({"N": N, "decay": p, "prec": name, "K": plan.rank, "ms": round(ms, 4),
+                            "coeffs_per_s": round((N + 1) / (ms * 1e-3), 1), "max_err_over_l1": err,
+                            "rows_checked": N + 1 if rows is None else int(len(rows))})
+                del plan
+    return out
+
+
 def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bulk")):
     """Mixed-degree batch: 4096 polynomials, degrees log-uniform in [16, 65536]."""
     degs = inputs.batch_degrees(4096, 16, 65536, seed=4)
@@ -387,6 +414,8 @@ def main():
         precs = ("fp64",) if args.prec == "fp64" else ("fp32_bulk",)
         if args.only == "batched":
             res = run_batched(thx, torch, inputs, oracle, dev, args.steps, precs=precs)
+        elif args.only == "sweep":
+            res = {"precision_sweep": run_sweep(thx, torch, inputs, oracle, dev, args.steps)}
         else:
             kinds = (args.kind,) if args.kind else ("ultra", "jac2cheb")
             res = run_config5(thx, torch, inputs, oracle, dev, args.steps, kinds=kinds, precs=precs)
@@ -454,6 +483,7 @@ def main():
 
     batch_res = run_batched(thx, torch, inputs, oracle, dev, args.steps)
     conf5 = run_config5(thx, torch, inputs, oracle, dev, args.steps)
+    sweep = run_sweep(thx, torch, inputs, oracle, dev, args.steps)
 
     copy_gbs = copy_bandwidth(torch)
 
@@ -512,6 +542,7 @@ def main():
                       "phases_ms_avg": phase_avg(tim32)},
         "batched": batch_res,
         "config5": conf5,
+        "precision_sweep": sweep,
         "cheb2leg_fp64": {"coeffs_per_s": round((N + 1) / (msc * 1e-3), 1), "ms_per_step": round(msc, 5),
                           "K": Kc, "max_err_over_l1": errc, "hankel_tol": 1e-17},
     }
