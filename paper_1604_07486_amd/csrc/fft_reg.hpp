@@ -3,8 +3,8 @@
 // A workgroup of NT threads transforms NB interleaved sequences of length M
 // (sequence c, element i at logical position i*NB + c).  Each thread keeps
 // E = M*NB/NT complex values in registers.  The transform is a sequence of
-// radix-R stages (R = 16 while possible, then one stage of 2, 4 or 8); the
-// inverse runs the radices in reverse order.  Between stages the values are
+// radix-R stages (R = RMAX while possible, then one stage of 2, 4 or 8, and a
+// radix-3 stage for M = 3 * 2^m); the inverse runs the radices in reverse order.  Between stages the values are
 // exchanged through LDS (padded one slot per 16 to spread the banks); the
 // first stage reads its inputs from registers and the last stage leaves its
 // outputs in registers, so callers load and store global memory directly in
@@ -25,15 +25,18 @@
 
 namespace thx {
 
-// forward radix of stage s for length M and largest radix RMAX (16, 8 or 4):
-// RMAX, RMAX, ..., then the remainder
-constexpr int nstages(int M, int RMAX)
-{
-    return ilog2(M) / ilog2(RMAX) + (ilog2(M) % ilog2(RMAX) ? 1 : 0);
-}
+// Lengths are M = 2^m or M = 3 * 2^m.  Forward radices of stage s for largest
+// power-of-two radix RMAX (16, 8 or 4): RMAX, RMAX, ..., the power-of-two
+// remainder, then one radix-3 stage when 3 divides M (last forward, first
+// inverse, so the first forward radix stays a power of two).
+constexpr int pow2_part(int M) { return M % 3 == 0 ? M / 3 : M; }
+constexpr int nstages2(int P, int RMAX) { return ilog2(P) / ilog2(RMAX) + (ilog2(P) % ilog2(RMAX) ? 1 : 0); }
+constexpr int nstages(int M, int RMAX) { return nstages2(pow2_part(M), RMAX) + (M % 3 == 0 ? 1 : 0); }
 constexpr int fwd_radix(int M, int s, int RMAX)
 {
-    return (s < ilog2(M) / ilog2(RMAX)) ? RMAX : (1 << (ilog2(M) % ilog2(RMAX)));
+    const int P = pow2_part(M);
+    return s >= nstages2(P, RMAX) ? 3
+                                  : ((s < ilog2(P) / ilog2(RMAX)) ? RMAX : (1 << (ilog2(P) % ilog2(RMAX))));
 }
 template <bool INV>
 constexpr int stage_radix(int M, int s, int RMAX)
@@ -49,6 +52,7 @@ constexpr int stage_ns(int M, int s, int RMAX)
     return ns;
 }
 // threads for M*NB points with at least min(M, RMAX) values per thread
+// (power-of-two M)
 constexpr int fft_threads(int M, int NB, int RMAX, int maxnt = 1024)
 {
     return (M * NB / (M < RMAX ? M : RMAX)) > maxnt ? maxnt : (M * NB / (M < RMAX ? M : RMAX));
@@ -104,12 +108,28 @@ __device__ __forceinline__ void dft4(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> 
     }
 }
 
+// radix-3 DFT: with s = x1 + x2, d = x1 - x2, y0 = x0 + s and
+// y1,2 = x0 - s/2 -+ i (sqrt(3)/2) d (forward; signs swapped for the inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2)
+{
+    constexpr T h = (T)0.86602540378443864676; // sqrt(3)/2
+    const cpx<T> sm = cadd(x1, x2), df = csub(x1, x2);
+    const cpx<T> t = {x0.x - (T)0.5 * sm.x, x0.y - (T)0.5 * sm.y};
+    const cpx<T> r = INV ? cpx<T>{-h * df.y, h * df.x} : cpx<T>{h * df.y, -h * df.x}; // -+ i h d
+    x0 = cadd(x0, sm);
+    x1 = cadd(t, r);
+    x2 = csub(t, r);
+}
+
 // Radix-R DFT in registers, R = R1 * R2 with input n = R2 n1 + n2 and output
 // k = k1 + R1 k2: DFT_R1 over n1, twiddle w_R^{n2 k1}, DFT_R2 over n2.
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft(cpx<T> *v)
 {
     if constexpr (R == 1) {
+    } else if constexpr (R == 3) {
+        dft3<T, INV>(v[0], v[1], v[2]);
     } else if constexpr (R == 2) {
         dft2<T, INV>(v[0], v[1]);
     } else if constexpr (R == 4) {
@@ -184,6 +204,7 @@ __device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restri
     if constexpr (R == 2) return;
     const cpx<T> w2 = tw[2 * e1];
     twmul<T, INV>(v[2], w2);
+    if constexpr (R == 3) return;
     const cpx<T> w3 = cmul(w1, w2);
     twmul<T, INV>(v[3], w3);
     if constexpr (R == 4) return;
@@ -212,7 +233,8 @@ struct RegFFT {
     static constexpr int R_FIRST = fwd_radix(M, 0, RMAX);
     static constexpr int R_LAST = fwd_radix(M, NS - 1, RMAX);
     static constexpr int LDS = lds_padded(M * NB);
-    static_assert(E * NT == M * NB && E % R_FIRST == 0 && E % R_LAST == 0, "elements per thread");
+    static_assert(E * NT == M * NB, "elements per thread");
+    static_assert(M % 3 != 0 || (M / 3 & (M / 3 - 1)) == 0, "length 2^m or 3 * 2^m");
 
     // logical position (i*NB + c) of register slot `slot` in the forward input layout
     __device__ static __forceinline__ void in_pos(int slot, int &pos, int &c)

@@ -1402,21 +1402,45 @@ __device__ __forceinline__ void xcd_map(int b, int items, int reps, int &item, i
 // at L2 = 256 measured 8% slower than 16.  FP32: 8192 (16384 spilled).
 template <typename T, int L2>
 constexpr int mp_tile() { return sizeof(T) == 4 ? 8192 : (L2 >= 512 ? 8192 : 4096); }
-template <typename T, int L2> constexpr int mp_tc() { return mp_tile<T, L2>() / L2 > 64 ? 64 : mp_tile<T, L2>() / L2; }
-template <typename T, int L2> constexpr int mp_nt() { return nthreads<L2, mp_tc<T, L2>()>(); }
+constexpr int64_t pow2_floor(int64_t x) { return x < 2 ? 1 : 2 * pow2_floor(x / 2); }
+// Columns of 3 * 2^m (lengths L = 3 * 2^k, which pad mixed batches less) take
+// radix-4 stages and one radix-3 stage with 12 values per thread (6 for columns
+// of 6), so that every radix divides the per-thread count; their tiles are the
+// largest power-of-two number of columns that fits.
+template <int L2> constexpr int col_rmax() { return L2 % 3 == 0 ? 4 : RMAX; }
+template <int L2> constexpr int col_e() { return L2 == 6 ? 6 : 12; }
+template <typename T, int L2>
+constexpr int mp_tc()
+{
+    return (int)std::min<int64_t>(64, pow2_floor(mp_tile<T, L2>() / L2));
+}
+template <typename T, int L2>
+constexpr int mp_nt()
+{
+    if constexpr (L2 % 3 == 0) return mp_tc<T, L2>() * L2 / col_e<L2>();
+    else return nthreads<L2, mp_tc<T, L2>()>();
+}
+template <typename T, int L2> using ColFFT = RegFFT<T, L2, mp_tc<T, L2>(), mp_nt<T, L2>(), col_rmax<L2>()>;
+
+// columns the three-pass kernels are built for: 2^m (2 ... 1024) or 3 * 2^m (6 ... 768)
+static bool column_length_ok(int64_t L2)
+{
+    const int64_t P = L2 % 3 == 0 ? L2 / 3 : L2;
+    return (P & (P - 1)) == 0 && (L2 % 3 == 0 ? (L2 >= 6 && L2 <= 768) : (L2 >= 2 && L2 <= 1024));
+}
 
 template <typename T>
 MultiPassGeom multipass_geom(int64_t L, int64_t row)
 {
     MultiPassGeom g;
     g.L = L;
-    const bool ok = (row == mp_row_short<T>() || row == mp_row_long<T>()) && L / row >= 2 && L / row <= 1024;
+    const bool ok = (row == mp_row_short<T>() || row == mp_row_long<T>()) && L % row == 0 &&
+                    column_length_ok(L / row);
     if (!ok) row = L / mp_row_short<T>() <= 512 ? mp_row_short<T>() : mp_row_long<T>();
     g.L1 = row;
     g.L2 = L / g.L1;
     const int64_t tile = sizeof(T) == 4 ? 8192 : (g.L2 >= 512 ? 8192 : 4096); // mp_tile<T, L2>
-    const int64_t tc = tile / g.L2;
-    g.TC = tc > 64 ? 64 : tc;
+    g.TC = std::min<int64_t>(64, pow2_floor(tile / g.L2));                    // mp_tc<T, L2>
     return g;
 }
 template MultiPassGeom multipass_geom<double>(int64_t, int64_t);
@@ -1441,7 +1465,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
 {
     constexpr int TC = mp_tc<T, L2>();
     constexpr int NT = mp_nt<T, L2>();
-    using F = RegFFT<T, L2, TC, NT, RMAX>;
+    using F = ColFFT<T, L2>;
     constexpr int64_t L = (int64_t)L1 * L2;
     __shared__ cpx<T> lds[F::LDS];
     constexpr int tiles = L1 / TC;
@@ -1705,7 +1729,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
     const cpx<T> *__restrict__ twL2)
 {
     constexpr int TC = mp_tc<T, L2>();
-    using F = RegFFT<T, L2, TC, mp_nt<T, L2>(), RMAX>;
+    using F = ColFFT<T, L2>;
     constexpr int E = F::E;
     // Outputs kept: positions a < n <= L/2 + 1 of each sequence.  In the
     // inverse's output layout, register slot e holds column position
@@ -1775,7 +1799,8 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
 }
 
 // Column lengths instantiated for each row length (L1 L2 <= MP_LMAX).
-#define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) \
+    X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768)
 
 template <typename T, int L1>
 bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,

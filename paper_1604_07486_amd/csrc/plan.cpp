@@ -55,6 +55,7 @@ inline void dfree(void *p)
 // for m <= n and zero beyond (the integer-difference, banded case).  Returns n.
 int64_t fill_banded_symbol(double *tsym_dev, int64_t nt, double dl, hipStream_t s);
 
+int64_t fft_length_for(int64_t n, thx_precision prec);
 int64_t next_pow2(int64_t x)
 {
     int64_t p = 1;
@@ -254,6 +255,25 @@ void *make_twiddles(thx_plan *p, int64_t M, int64_t count, hipStream_t s, int ke
     return t32;
 }
 
+// Circulant length for a Toeplitz product of n lanes: the smallest 2^k >= 2n - 2,
+// or 3 * 2^(k-2) when that is long enough and the three-pass path takes it with
+// columns of at least 6 entries; the Toeplitz product is exact for any length
+// >= 2n - 2, and the shorter length moves 3/4 of the bytes (members of mixed
+// batches fall in whichever is nearer).  THX_POW2_LENGTHS=1 keeps powers of two.
+int64_t fft_length_for(int64_t n, thx_precision prec)
+{
+    const int64_t need = std::max<int64_t>(64, 2 * n - 2);
+    const int64_t p2 = next_pow2(need);
+    if (const char *e = getenv("THX_POW2_LENGTHS"))
+        if (atoi(e) != 0) return p2;
+    const bool f64 = prec == THX_FP64;
+    const int64_t lmax = f64 ? lds_max_len<double>() : lds_max_len<float>();
+    const int64_t row = f64 ? mp_row_short<double>() : mp_row_short<float>();
+    const int64_t t = p2 / 4 * 3;
+    if (t >= need && t > lmax && t >= 6 * row && t <= MP_LMAX) return t;
+    return p2;
+}
+
 // FFT of the embedded symbol in double precision, natural order, scaled by 1/L.
 double *symbol_spectrum64(thx_plan *p, hipStream_t s)
 {
@@ -430,7 +450,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
 
 void build_fft(thx_plan *p, hipStream_t s)
 {
-    p->L = std::max<int64_t>(64, next_pow2(2 * p->nc - 2));
+    p->L = fft_length_for(p->nc, p->prec);
     if (p->L > ((int64_t)1 << 22)) throw std::invalid_argument("L");
     run_pchol(p, s);
     p->alias = dalloc<double>(2);
@@ -1258,7 +1278,7 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
         const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
                             (!(flags & THX_FLAG_FORCE_FFT) && N <= direct_crossover()) || N < 2;
         const int64_t nc = parity ? N / 2 + 1 : N + 1;
-        groups[direct ? 0 : std::max<int64_t>(64, next_pow2(2 * nc - 2))].push_back(i);
+        groups[direct ? 0 : fft_length_for(nc, prec)].push_back(i);
     }
     b->total = acc;
     thx_status result = THX_OK;

@@ -169,6 +169,51 @@ def test_leg2cheb_lds_radix(thx, N, prec, radix, monkeypatch):
     assert plan.path == 1 and plan.lds_radix == radix
 
 
+# circulant lengths 3 * 2^k (the three-pass path with columns of 3 * 2^m: radix-4
+# stages and one radix-3 stage), both row lengths where the columns allow them,
+# the alias at L = 2n - 2 (N = L), several vectors, other kinds; and the same
+# sizes with power-of-two lengths only (THX_POW2_LENGTHS)
+@pytest.mark.parametrize("N,prec,row,batch,L", [
+    (10000, 0, 2048, 2, 12288), (12288, 0, 0, 1, 12288), (20000, 0, 2048, 1, 24576), (20000, 0, 4096, 3, 24576),
+    (45000, 0, 4096, 1, 49152), (98304, 0, 2048, 1, 98304), (700000, 0, 0, 1, 786432),
+    (20000, 1, 4096, 2, 24576), (45000, 1, 8192, 1, 49152), (45000, 1, 4096, 1, 49152),
+    (3 << 20, 0, 0, 1, 3 << 20), (3 << 20, 1, 0, 1, 3 << 20),
+])
+def test_leg2cheb_three_times_pow2_lengths(thx, N, prec, row, batch, L, monkeypatch):
+    if row:
+        monkeypatch.setenv("THX_ROW_LEN", str(row))
+    plan, alpha, got = _run(thx, thx.LEG2CHEB, N, prec, flags=thx.FLAG_FORCE_FFT, seed=N + row, batch=batch)
+    assert plan.path == 2 and plan.fft_length == L
+    rows_, cols, tile = plan.fft_geometry()
+    print(f"  geometry rows={rows_} cols={cols} tile={tile}", flush=True)
+    bar = TOL64 if prec == 0 else TOL32
+    for i in range(batch):
+        if N > 20000:
+            r = inputs.sample_rows(N, 256, seed=i)
+            err = float(np.max(np.abs(got[i][r] - oracle.matvec("leg2cheb", alpha[i], rows=r))) / np.sum(np.abs(alpha[i])))
+        else:
+            err = _err(got[i], oracle.matvec("leg2cheb", alpha[i]), alpha[i])
+        print(f"  vector {i}: K={plan.rank} L={plan.fft_length} err={err:.3e}", flush=True)
+        assert err < bar
+
+
+@pytest.mark.parametrize("kind,params,N,L", [
+    (4, (0.5, -0.25), 10000, 24576),   # Laguerre: n = N + 1 lanes, two ranks per complex slot
+    (1, (), 20000, 24576),             # cheb2leg: row 0 direct
+    (2, (0.75, 0.25), 40000, 49152),   # ultraspherical, case 2
+])
+def test_three_times_pow2_lengths_other_kinds(thx, kind, params, N, L):
+    plan, _ = _check_full(thx, kind, N, thx.FP64, params, flags=thx.FLAG_FORCE_FFT, seed=N,
+                          tol=1e-17 if kind == 1 else None, p=1.5 if kind == 1 else 1.0, scale_bar=(kind == 2))
+    assert plan.path == 2 and plan.fft_length == L
+
+
+def test_pow2_lengths_switch(thx, monkeypatch):
+    monkeypatch.setenv("THX_POW2_LENGTHS", "1")
+    plan, _ = _check_full(thx, thx.LEG2CHEB, 20000, thx.FP64, flags=thx.FLAG_FORCE_FFT, seed=3)
+    assert plan.fft_length == 32768
+
+
 # several slots per forward-column-pass workgroup (THX_P1_BLOCKS is read at plan
 # creation): 1 puts every slot of a vector's tile in one workgroup, 100 leaves
 # ragged slot groups
@@ -191,7 +236,7 @@ def test_leg2cheb_p1_slot_groups(thx, N, prec, batch, p1, monkeypatch):
 @pytest.mark.parametrize("N,prec,row,batch", [
     (8192, 0, 2048, 3), (5000, 0, 2048, 1), (6000, 0, 2048, 9),                          # columns of 4
     (8192, 0, 4096, 2), (5000, 0, 4096, 1), (16383, 0, 4096, 1), (16384, 0, 4096, 11),   # 2, 2, 4, 4
-    (16384, 1, 4096, 3), (10000, 1, 8192, 5), (32768, 1, 8192, 1), (24000, 1, 8192, 2),  # 4, 2, 4, 4
+    (16384, 1, 4096, 3), (10000, 1, 8192, 5), (32768, 1, 8192, 1), (30000, 1, 8192, 2),  # 4, 2, 4, 4
 ])
 def test_leg2cheb_fused_columns(thx, N, prec, row, batch, monkeypatch):
     monkeypatch.setenv("THX_P1_BLOCKS", "-1")
@@ -212,7 +257,7 @@ def test_leg2cheb_fused_columns(thx, N, prec, row, batch, monkeypatch):
 
 @pytest.mark.parametrize("kind,params,N", [
     (4, (0.5, -0.25), 3000),          # Laguerre: no parity split, two ranks per complex slot
-    (1, (), 9000),                    # cheb2leg: row 0 computed directly
+    (1, (), 14000),                   # cheb2leg: row 0 computed directly
 ])
 def test_fused_columns_other_kinds(thx, kind, params, N, monkeypatch):
     monkeypatch.setenv("THX_P1_BLOCKS", "-1")
