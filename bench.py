@@ -45,7 +45,7 @@ def parse():
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "RUN_LOG"), default=None,
                     help="summarise two rocprofv3 --pmc runs of --headline-only --copy-calibration "
                          "(FETCH_SIZE, WRITE_SIZE) into " + "profiles/<...>.txt and exit (no GPU use)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -57,12 +57,16 @@ def parse():
 COPY_BYTES = 512 << 20
 
 # Measured HBM traffic of the dominant kernel (row pass of the headline plan),
-# valid only for the kernel sources it was taken with.
+# valid only for the device sources it was taken with, the same template
+# instantiation (row length) and the same algorithmic bytes per launch.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_leg2cheb_N2p20_fp64_hbm_traffic.txt")
-TRAFFIC_KERNEL = "k_mp_p2<double, 2048>"
 TRAFFIC_SOURCES = ["paper_1604_07486_amd/csrc/kernels.hip", "paper_1604_07486_amd/csrc/fft_reg.hpp",
-                   "paper_1604_07486_amd/csrc/thx_device.hpp", "paper_1604_07486_amd/csrc/launch.hpp",
-                   "paper_1604_07486_amd/csrc/plan.cpp"]
+                   "paper_1604_07486_amd/csrc/thx_device.hpp", "paper_1604_07486_amd/csrc/launch.hpp"]
+
+
+def row_kernel_name(plan):
+    """Template instantiation of the row pass the plan launches (its row length)."""
+    return f"k_mp_p2<double, {plan.fft_geometry()[0]}>" if plan.path == 2 else None
 
 
 def cpu_model():
@@ -115,20 +119,27 @@ def pmc_dispatches(db, counter):
     return [(re.sub(r"\(.*", "", k).replace("void ", "").replace("thx::", ""), v) for _, k, v in rows]
 
 
-def write_traffic(fetch_db, write_db):
+def write_traffic(fetch_db, write_db, run_log):
     """Average FETCH_SIZE / WRITE_SIZE of the execute dispatches of the row pass, scaled by what the
-    same counters read for the 512 MiB device copy of the same run."""
+    same counters read for the 512 MiB device copy of the same run.  `run_log` holds the JSON line
+    of the profiled `--headline-only` run: the row-pass instantiation it executed and that launch's
+    algorithmic bytes."""
+    info = None
+    for line in open(run_log):
+        if line.startswith("{") and '"headline_only"' in line:
+            info = json.loads(line)
+    kernel, algo = info["row_kernel"], info["row_bytes_per_launch"]
     out = {}
     for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         d = pmc_dispatches(db, counter)
-        row = [v for k, v in d if k == TRAFFIC_KERNEL]
+        row = [v for k, v in d if k == kernel]
         big = max(row)
         row = [v for v in row if v > 0.5 * big]           # drops the plan's symbol transform
         copy = max(v for k, v in d if "copyBuffer" in k)   # the 512 MiB calibration copy
         out[key] = (sum(row) / len(row), len(row), (COPY_BYTES / 1024) / copy)
     traffic = out["fetch"][0] * 1024 * out["fetch"][2] + out["write"][0] * 1024 * out["write"][2]
     lines = [
-        "# HBM traffic of the row pass (k_mp_p2<double, 2048>), leg2cheb N=2^20 FP64 headline plan",
+        f"# HBM traffic of the row pass ({kernel}), leg2cheb N=2^20 FP64 headline plan",
         "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
         "# execute dispatches; factors = bytes of the 512 MiB device copy in the same run / counter.",
         "# Commands (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp):",
@@ -137,8 +148,8 @@ def write_traffic(fetch_db, write_db):
         "#   rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/fp64_WRITE_SIZE -o pmc -- python3 $R/bench.py "
         "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
         "#   python3 bench.py --write-traffic $OUT/pmc/fp64_FETCH_SIZE/pmc_results.db "
-        "$OUT/pmc/fp64_WRITE_SIZE/pmc_results.db",
-        f"kernel = {TRAFFIC_KERNEL}",
+        "$OUT/pmc/fp64_WRITE_SIZE/pmc_results.db $OUT/pmc/fp64_FETCH_SIZE.log",
+        f"kernel = {kernel}",
         "phase = row",
         f"fetch_kib_per_dispatch = {out['fetch'][0]:.1f}",
         f"write_kib_per_dispatch = {out['write'][0]:.1f}",
@@ -146,6 +157,7 @@ def write_traffic(fetch_db, write_db):
         f"fetch_factor = {out['fetch'][2]:.4f}",
         f"write_factor = {out['write'][2]:.4f}",
         f"traffic_bytes_per_launch = {traffic:.0f}",
+        f"algorithmic_bytes_per_launch = {algo}",
         f"source_sha256 = {source_digest()}",
     ]
     with open(TRAFFIC_FILE, "w") as fh:
@@ -153,16 +165,19 @@ def write_traffic(fetch_db, write_db):
     print("\n".join(lines))
 
 
-def measured_traffic(phase):
+def measured_traffic(phase, kernel, algo_bytes):
     """Bytes per launch from the committed counter summary, or None if it is absent, for another
-    kernel, or taken with other kernel sources."""
+    phase or kernel instantiation (the plan's row length picks the template), for a launch of other
+    algorithmic bytes (another rank or slot chunking), or taken with other device sources."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("phase") != phase or kv.get("source_sha256") != source_digest():
+        if kv.get("phase") != phase or kv.get("kernel") != kernel or kv.get("source_sha256") != source_digest():
+            return None
+        if int(kv["algorithmic_bytes_per_launch"]) != int(algo_bytes):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -403,9 +418,12 @@ def main():
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase="row")
         parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
+        es = 16 if prec == thx.FP64 else 8
+        row_bytes = phase_bytes("row", es, plan.rank, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
         print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
                           "K": plan.rank, "L": plan.fft_length, "row_ms_avg": phase_avg(tim).get("row"),
-                          "phases_ms_avg": phase_avg(parts)}), flush=True)
+                          "row_kernel": row_kernel_name(plan) if prec == thx.FP64 else None,
+                          "row_bytes_per_launch": row_bytes, "phases_ms_avg": phase_avg(parts)}), flush=True)
         return
 
     import oracle
@@ -455,7 +473,7 @@ def main():
     roof = None
     if dbytes is not None:
         achieved = dbytes / (davg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(dname)
+        traffic = measured_traffic(dname, row_kernel_name(plan), dbytes)
         roof = {"kernel": dname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
