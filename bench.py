@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline timed loop (for profiler runs)")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--prec", choices=["fp64", "fp32", "tail32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
     ap.add_argument("--only", choices=["batched", "config5", "sweep"], default=None,
                     help="run one secondary section only (profiler runs) and print its JSON")
@@ -291,11 +291,12 @@ def run_sweep(thx, torch, inputs, oracle, dev, steps):
     return out
 
 
-def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bulk")):
+def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bulk", "fp64_tail32")):
     """Mixed-degree batch: 4096 polynomials, degrees log-uniform in [16, 65536]."""
     degs = inputs.batch_degrees(4096, 16, 65536, seed=4)
     batch_res = {}
-    for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7)):
+    for pname, prec, tolh in (("fp64", thx.FP64, 1e-15), ("fp32_bulk", thx.FP32_BULK, 1e-7),
+                              ("fp64_tail32", thx.FP64_TAIL32, 1e-15)):
         if pname not in precs:
             continue
         flat = np.concatenate([inputs.coeffs(int(n), 1.0, seed=1000 + i) for i, n in enumerate(degs)])
@@ -412,13 +413,13 @@ def main():
     b = torch.empty_like(a)
 
     if args.headline_only:
-        prec = thx.FP64 if args.prec == "fp64" else thx.FP32_BULK
-        plan = thx.Plan(thx.LEG2CHEB, N, 1e-15 if prec == thx.FP64 else 1e-7, prec)
+        prec = {"fp64": thx.FP64, "fp32": thx.FP32_BULK, "tail32": thx.FP64_TAIL32}[args.prec]
+        plan = thx.Plan(thx.LEG2CHEB, N, 1e-7 if prec == thx.FP32_BULK else 1e-15, prec)
         plan.autotune(1)
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase="row")
         parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
-        es = 16 if prec == thx.FP64 else 8
+        es = 8 if prec == thx.FP32_BULK else 16
         row_bytes = phase_bytes("row", es, plan.rank, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
         print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
                           "K": plan.rank, "L": plan.fft_length, "row_ms_avg": phase_avg(tim).get("row"),
@@ -429,7 +430,7 @@ def main():
     import oracle
 
     if args.only:
-        precs = ("fp64",) if args.prec == "fp64" else ("fp32_bulk",)
+        precs = ({"fp64": "fp64", "fp32": "fp32_bulk", "tail32": "fp64_tail32"}[args.prec],)
         if args.only == "batched":
             res = run_batched(thx, torch, inputs, oracle, dev, args.steps, precs=precs)
         elif args.only == "sweep":
@@ -490,6 +491,17 @@ def main():
     err32 = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
     K32 = plan32.rank
     del plan32
+
+    # ---- FP64 with the small-pivot ranks in single precision (same tolerance) ----
+    plant = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64_TAIL32)
+    plant.autotune(1)
+    mst, _ = time_plan(thx, torch, plant, a, b, args.steps, args.warmup)
+    timt = phase_breakdown(torch, plant, a, b, max(5, args.steps // 5))
+    errt = sampled_error(oracle, "leg2cheb", alpha, b.cpu().numpy(), rows)
+    tail32 = {"coeffs_per_s": round((N + 1) / (mst * 1e-3), 1), "ms_per_step": round(mst, 5),
+              "K": plant.rank, "fp32_slots": plant.tail_slots, "max_err_over_l1": errt, "bar": 3e-15,
+              "hankel_tol": 1e-15, "phases_ms_avg": phase_avg(timt)}
+    del plant
 
     # ---- Chebyshev -> Legendre at the same N (Sec. 5.1) ----
     planc = thx.Plan(thx.CHEB2LEG, N, 1e-17, thx.FP64)
@@ -558,6 +570,7 @@ def main():
         "fp32_bulk": {"coeffs_per_s": round((N + 1) / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 5),
                       "K": K32, "max_err_over_l1": err32, "bar": 5e-6, "hankel_tol": 1e-7,
                       "phases_ms_avg": phase_avg(tim32)},
+        "fp64_tail32": tail32,
         "batched": batch_res,
         "config5": conf5,
         "precision_sweep": sweep,

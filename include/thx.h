@@ -53,9 +53,20 @@ typedef enum {
 
 typedef enum {
     THX_FP64 = 0,      /* every step in double precision                              */
-    THX_FP32_BULK = 1  /* FFTs and rank accumulation in single precision; Lambda and
+    THX_FP32_BULK = 1, /* FFTs and rank accumulation in single precision; Lambda and
                           Gamma ratios, the pivoted Cholesky and D1, D2 in double;
                           the dense path (3) in split bfloat16 with FP32 accumulation */
+    THX_FP64_TAIL32 = 2 /* THX_FP64, except that on the three-pass path (2) the
+                          trailing ranks whose pivots are at most tol * 2^23 of
+                          the largest diagonal of H (Sec. 2.1: the rank-r term of
+                          the Hankel approximation is of size pivot_r) run their
+                          FFTs and partial sums in single precision: their
+                          rounding then adds at most ~tol/4 of ||alpha||_1, below
+                          the truncation the tolerance allows, and their
+                          intermediates take half the bytes.  On by default for
+                          L >= 2^16; thx_plan_autotune decides for its batch from
+                          L = 8192 up (and may keep those ranks in double);
+                          thx_plan_tail_slots says how many run in single */
 } thx_precision;
 
 /* plan flags */
@@ -123,6 +134,9 @@ thx_status thx_plan_destroy(thx_plan *plan);
  * precision in O(N).  For a multi-stage plan, path and rank describe the first
  * stage (path 3 the whole conversion). */
 int32_t thx_plan_rank(const thx_plan *plan);
+/* THX_FP64_TAIL32 plans: FFT slots run in single precision (summed over the
+ * stages); 0 for other plans and when every slot runs in double; -1 for NULL. */
+int32_t thx_plan_tail_slots(const thx_plan *plan);
 int32_t thx_plan_rank_part(const thx_plan *plan, int part);
 int64_t thx_plan_fft_length(const thx_plan *plan);
 int32_t thx_plan_path(const thx_plan *plan);

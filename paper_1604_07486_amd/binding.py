@@ -19,7 +19,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # enums (include/thx.h)
 LEG2CHEB, CHEB2LEG, ULTRA2ULTRA, JAC2JAC, LAG2LAG, JAC2CHEB, CHEB2JAC = 0, 1, 2, 3, 4, 5, 6
-FP64, FP32_BULK = 0, 1
+FP64, FP32_BULK, FP64_TAIL32 = 0, 1, 2
 FLAG_FORCE_DIRECT, FLAG_FORCE_FFT, FLAG_NO_DENSE, FLAG_AUTOTUNE = 1, 2, 4, 8
 PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct", "dense", "scan"]
 STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_TOL_NOT_REACHED",
@@ -51,6 +51,7 @@ _sig("thx_plan_launch_shape", ctypes.c_int, _vp, ctypes.POINTER(_i32), ctypes.PO
 _sig("thx_plan_lds_radix", _i32, _vp)
 _sig("thx_plan_p1_blocks", _i32, _vp)
 _sig("thx_plan_fused_columns", _i32, _vp)
+_sig("thx_plan_tail_slots", _i32, _vp)
 _sig("thx_plan_partial_groups", _i32, _vp, _i64)
 _sig("thx_plan_achieved_tol", _dbl, _vp, ctypes.c_int)
 _sig("thx_plan_factors", ctypes.c_int, _vp, ctypes.c_int, _dp, ctypes.POINTER(_i32),
@@ -154,6 +155,11 @@ class Plan:
     def fused_columns(self) -> bool:
         """True if the forward column pass runs inside the row pass (columns of 2 or 4)."""
         return int(_lib.thx_plan_fused_columns(self._h)) == 1
+
+    @property
+    def tail_slots(self) -> int:
+        """FFT slots run in single precision (FP64_TAIL32 plans; 0 otherwise)."""
+        return int(_lib.thx_plan_tail_slots(self._h))
 
     @property
     def lds_radix(self) -> int:

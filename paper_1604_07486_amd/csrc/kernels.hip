@@ -255,6 +255,7 @@ __global__ __launch_bounds__(1024) void k_pchol_select(PcholArgs a, int r)
                 st->cur_p[q] = idx;
                 st->cur_piv[q] = v;
                 st->piv[q][r] = idx;
+                st->pval[q][r] = v;
                 go = 1;
             }
         }
@@ -514,7 +515,8 @@ void launch_alias_sums(const double *ell64, int64_t nc_ell, int S, int parts, in
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
-                                                double *beta, int64_t N0, const cpx<T> *W, int G, int64_t nc,
+                                                double *beta, int64_t N0, const cpx<T> *W, int G,
+                                                const cpx<float> *W2, int G2, int64_t nc,
                                                 int64_t batch, int64_t L, const double *alias,
                                                 const double *tsym, const double *row0)
 {
@@ -545,6 +547,15 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
         wy += (double)v.y;
         wsum += (double)v.x + (double)v.y;
     }
+    if (G2 > 0) {
+        const cpx<float> *W2a = W2 + b * nc + a;
+        for (g = 0; g < G2; ++g) {
+            const cpx<float> v = W2a[(int64_t)g * gstride];
+            wx += (double)v.x;
+            wy += (double)v.y;
+            wsum += (double)v.x + (double)v.y;
+        }
+    }
     if (k.parity) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -570,17 +581,18 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
 template <typename T>
 void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                    int64_t ld, double *beta, int64_t N, int64_t batch, const void *Wpart, int G,
-                   int64_t nc, int64_t L, const double *alias, const double *tsym, const double *row0,
-                   hipStream_t s)
+                   const void *Wpart2, int G2, int64_t nc, int64_t L, const double *alias,
+                   const double *tsym, const double *row0, hipStream_t s)
 {
     const int nt = 256;
     const int64_t lanes = k.parity ? N / 2 + 1 : N + 1;
     dim3 grid((unsigned)((lanes + nt - 1) / nt), (unsigned)batch);
     k_unpack<T><<<grid, nt, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, (const cpx<T> *)Wpart, G,
-                                    nc, batch, L, alias, tsym, row0);
+                                    (const cpx<float> *)Wpart2, Wpart2 ? G2 : 0, nc, batch, L, alias, tsym,
+                                    row0);
 }
-template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
-template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
+template void launch_unpack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
+template void launch_unpack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, double *, int64_t, int64_t, const void *, int, const void *, int, int64_t, int64_t, const double *, const double *, const double *, hipStream_t);
 
 // Row 0 computed directly when the Hankel part is PSD only on indices >= 1
 // (cheb2leg, Sec. 5.1; Jacobi case 3, Sec. 5.3): rows/columns >= 1 go through
@@ -1427,6 +1439,11 @@ static bool column_length_ok(int64_t L2)
 {
     const int64_t P = L2 % 3 == 0 ? L2 / 3 : L2;
     return (P & (P - 1)) == 0 && (L2 % 3 == 0 ? (L2 >= 6 && L2 <= 768) : (L2 >= 2 && L2 <= 1024));
+}
+
+bool multipass_ok(int64_t L, int64_t L1)
+{
+    return L1 > 0 && L % L1 == 0 && column_length_ok(L / L1);
 }
 
 template <typename T>

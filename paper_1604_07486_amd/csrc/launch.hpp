@@ -41,6 +41,7 @@ struct PcholState {
     double dmax0[2];
     double dfinal[2];
     int piv[2][KMAX];
+    double pval[2][KMAX]; // pivot values (residual diagonal at p_r when chosen)
     double R[2][KMAX][KMAX]; // R[q][r][i] = normalised column i of part q at pivot p_r
 };
 
@@ -98,10 +99,13 @@ template <typename T>
 void launch_pack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                  int64_t ld, int64_t N, int64_t batch, void *X /*cpx<T> [batch][nc]*/, int64_t nc,
                  hipStream_t s);
+// Wpart2 (may be null with G2 = 0): further partial sums in single precision, from
+// the ranks a mixed-precision plan runs in FP32
 template <typename T>
 void launch_unpack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                    int64_t ld, double *beta, int64_t N, int64_t batch,
-                   const void *Wpart /*cpx<T> [G][batch][nc]*/, int G, int64_t nc, int64_t L,
+                   const void *Wpart /*cpx<T> [G][batch][nc]*/, int G,
+                   const void *Wpart2 /*cpx<float> [G2][batch][nc]*/, int G2, int64_t nc, int64_t L,
                    const double *alias /*launch_alias_sums*/, const double *tsym,
                    const double *row0, hipStream_t s);
 // the two plan constants of the circulant alias correction at n - 1 = L/2, from the
@@ -179,6 +183,8 @@ struct MultiPassGeom {
 // geometry for length L; `row` selects mp_row_short / mp_row_long, any other
 // value (or one that leaves the columns outside 2..1024) the default
 template <typename T> MultiPassGeom multipass_geom(int64_t L, int64_t row = 0);
+// true when the three-pass kernels are built for rows of L1 points and columns of L / L1
+bool multipass_ok(int64_t L, int64_t L1);
 // P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr),
 // `spb` consecutive slots per workgroup
 template <typename T>

@@ -172,6 +172,15 @@ struct thx_plan {
     void *twL1 = nullptr, *twL2 = nullptr, *twA = nullptr; // three-pass tables
     double *tw64_keep[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *pivots[2] = {nullptr, nullptr}; // host copies
+    std::vector<double> prel[2];             // pivot value / largest diagonal, per rank
+    int S_full = 0; // slots of the whole factorisation (S: those run in this plan's precision)
+    // THX_FP64_TAIL32: the trailing slots, whose pivots are so small that single
+    // precision rounds them below the Hankel tolerance, run as a single-precision
+    // plan of their own (same Cholesky columns, symbol and length); its partial
+    // sums join this plan's in the final step
+    bool tail_req = false;
+    bool tail_on = false;
+    thx_plan *tail = nullptr;
     // workspace (grown on demand; executions of one plan must be serialised)
     int64_t ws_batch = 0;
     void *X = nullptr, *Wp = nullptr, *U = nullptr;
@@ -225,6 +234,7 @@ struct thx_plan {
         dfree(tmp2);
         dfree(dense);
         dfree(dense_bf);
+        delete tail;
         delete next;
     }
 };
@@ -267,7 +277,7 @@ int64_t fft_length_for(int64_t n, thx_precision prec)
     const int64_t p2 = next_pow2(need);
     if (const char *e = getenv("THX_POW2_LENGTHS"))
         if (atoi(e) != 0) return p2;
-    const bool f64 = prec == THX_FP64;
+    const bool f64 = prec != THX_FP32_BULK;
     const int64_t lmax = f64 ? lds_max_len<double>() : lds_max_len<float>();
     const int64_t row = f64 ? mp_row_short<double>() : mp_row_short<float>();
     const int64_t t = p2 / 4 * 3;
@@ -441,12 +451,84 @@ void run_pchol(thx_plan *p, hipStream_t s)
         if (hs.K[q] >= kcap && hs.dfinal[q] > p->tol) p->tol_reached = false;
         p->pivots[q] = new int32_t[std::max(1, hs.K[q])];
         for (int r = 0; r < hs.K[q]; ++r) p->pivots[q][r] = hs.piv[q][r];
+        p->prel[q].resize(std::max(0, hs.K[q]));
+        for (int r = 0; r < hs.K[q]; ++r) p->prel[q][r] = hs.dmax0[q] > 0 ? hs.pval[q][r] / hs.dmax0[q] : 0.0;
     }
     p->S = p->parts == 2 ? std::max(p->K[0], p->K[1]) : (p->K[0] + 1) / 2;
+    p->S_full = p->S;
     dfree(d);
     dfree(st);
     dfree(pv);
     dfree(pi);
+}
+
+// ---- FP64 plans with a single-precision tail (THX_FP64_TAIL32) ----
+// Slot r's term D_l~r T D_l~r x is of size piv_r / max diag(H) relative to the
+// largest.  Run in single precision, a whole plan whose first pivot is the
+// largest diagonal errs by at most 2.7e-8 of ||alpha||_1 (leg2cheb at 2^16 and
+// 2^20 with every rank in single precision, measured), so slots whose every
+// pivot is at most tol * 2^23 of the largest diagonal add at most ~tol/4
+// together, under the truncation the Hankel tolerance already allows
+// (2 tol ||alpha||_1 for leg2cheb).
+constexpr double TAIL32_PIVOT_GAIN = 8388608.0; // 2^23
+constexpr int64_t TAIL32_MIN_L = 8192;             // built from here (single-precision rows of 4096, columns >= 2)
+constexpr int64_t TAIL32_ON_L = (int64_t)1 << 16; // on by default from here: shorter single transforms are
+                                                  // latency-bound; the autotuner decides for its batch
+
+// first slot from which every later slot has only small pivots
+int tail_first_slot(const thx_plan *p)
+{
+    double gain = TAIL32_PIVOT_GAIN;
+    // THX_TAIL32_LOG2GAIN: log2 of the gain (measurements of the error it trades)
+    if (const char *e = getenv("THX_TAIL32_LOG2GAIN")) gain = std::ldexp(1.0, atoi(e));
+    const double lim = p->tol * gain;
+    auto small = [&](int q, int r) { return r >= p->K[q] || p->prel[q][r] <= lim; };
+    auto slot_small = [&](int sl) {
+        return p->parts == 2 ? small(0, sl) && small(1, sl) : small(0, 2 * sl) && small(0, 2 * sl + 1);
+    };
+    int s0 = p->S;
+    while (s0 > 0 && slot_small(s0 - 1)) --s0;
+    return s0;
+}
+
+void build_tail(thx_plan *p, const double *spec, hipStream_t s)
+{
+    if (p->L < TAIL32_MIN_L) return;
+    const MultiPassGeom g = multipass_geom<float>(p->L, 0);
+    if (!multipass_ok(p->L, g.L1)) return;
+    const int s0 = tail_first_slot(p);
+    if (s0 >= p->S) return;
+    thx_plan *t = new thx_plan();
+    p->tail = t; // owned by p from here, also on a later error
+    t->kind = p->kind;
+    t->kd = p->kd; // device tables stay owned by p
+    std::memcpy(t->params, p->params, sizeof(t->params));
+    t->N = p->N;
+    t->tol = p->tol;
+    t->prec = THX_FP32_BULK;
+    t->flags = p->flags;
+    t->parts = p->parts;
+    t->nc = p->nc;
+    t->ncs = p->ncs;
+    for (int q = 0; q < 2; ++q) {
+        t->npart[q] = p->npart[q];
+        t->a0[q] = p->a0[q];
+    }
+    t->L = p->L;
+    t->path = 2;
+    t->S = t->S_full = p->S - s0;
+    t->geom = g;
+    t->ell32 = dalloc<float>(2 * (int64_t)t->S * p->ncs);
+    launch_cast(p->ell64 + 2 * (int64_t)s0 * p->ncs, t->ell32, 2 * (int64_t)t->S * p->ncs, s);
+    launch_check();
+    t->twL1 = make_twiddles(t, g.L1, g.L1, s, 0);
+    t->twL2 = make_twiddles(t, g.L2, g.L2, s, 1);
+    t->twA = make_twiddles(t, p->L, g.L1, s, 2);
+    t->that = dalloc<char>((int64_t)t->esize() * p->L);
+    launch_reorder<float>(spec, t->that, p->L, g.L1, g.L2, 2, s);
+    launch_check();
+    p->tail_on = p->L >= TAIL32_ON_L;
+    if (p->tail_on) p->S = s0;
 }
 
 void build_fft(thx_plan *p, hipStream_t s)
@@ -500,6 +582,7 @@ void build_fft(thx_plan *p, hipStream_t s)
         if (f64) launch_reorder<double>(spec, p->that, L, g.L1, g.L2, 2, s);
         else launch_reorder<float>(spec, p->that, L, g.L1, g.L2, 2, s);
         launch_check();
+        if (p->tail_req) build_tail(p, spec, s);
     }
     dfree(spec);
     hip_check(hipStreamSynchronize(s));
@@ -699,7 +782,8 @@ thx_status create_plan(thx_plan **out, thx_kind kind, const double *params, int 
 {
     if (!out) return THX_INVALID_ARGUMENT;
     *out = nullptr;
-    if (degree < 0 || !(tol > 0) || !(tol < 1) || (prec != THX_FP64 && prec != THX_FP32_BULK))
+    if (degree < 0 || !(tol > 0) || !(tol < 1) ||
+        (prec != THX_FP64 && prec != THX_FP32_BULK && prec != THX_FP64_TAIL32))
         return THX_INVALID_ARGUMENT;
     double pv[4] = {0, 0, 0, 0};
     thx_status vs = validate_kind(kind, params, nparams, pv);
@@ -741,7 +825,8 @@ thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const 
     std::memcpy(p->params, pv, sizeof(p->params));
     p->N = degree;
     p->tol = tol;
-    p->prec = prec;
+    p->prec = prec == THX_FP64_TAIL32 ? THX_FP64 : prec;
+    p->tail_req = prec == THX_FP64_TAIL32;
     p->flags = flags;
     p->kd.kind = jac ? (int)THX_JAC2JAC : (int)kind;
     p->kd.parity = (kind == THX_LEG2CHEB || kind == THX_CHEB2LEG || kind == THX_ULTRA2ULTRA) ? 1 : 0;
@@ -826,6 +911,7 @@ struct PhaseTimer {
 
 void ensure_workspace(thx_plan *p, int64_t batch)
 {
+    if (p->tail) ensure_workspace(p->tail, batch);
     if (batch <= p->ws_batch) return;
     if (p->path == 4) {
         dfree(p->sfx_tot);
@@ -846,7 +932,8 @@ void ensure_workspace(thx_plan *p, int64_t batch)
     p->ws_batch = 0;
     const size_t es = p->esize();
     p->X = dalloc<char>((int64_t)(es * (size_t)(batch * p->ncs)));
-    p->Gmax = std::max(1, p->S);
+    const int slots = std::max(p->S, p->S_full); // the tail may be switched off
+    p->Gmax = std::max(1, slots);
     p->Wp = dalloc<char>((int64_t)(es * (size_t)((int64_t)p->Gmax * batch * p->ncs)));
     p->row0 = dalloc<double>(batch);
     if (p->row0_direct) p->row0_part = dalloc<double>(batch * ROW0_PMAX);
@@ -857,7 +944,7 @@ void ensure_workspace(thx_plan *p, int64_t batch)
         const int64_t per = (int64_t)es * p->L * batch;
         int64_t sc = std::max<int64_t>(1, ((int64_t)8 << 30) / per);
         if (const char *e = getenv("THX_SLOT_CHUNK")) sc = std::max<int64_t>(1, std::min<int64_t>(sc, atoll(e)));
-        sc = std::min<int64_t>(sc, std::max(1, p->S));
+        sc = std::min<int64_t>(sc, std::max(1, slots));
         p->U_slots = sc;
         p->U = dalloc<char>(per * sc);
     }
@@ -872,14 +959,17 @@ int p1_slots_per_block(const thx_plan *p, int ns, int64_t batch)
     return (int)std::max<int64_t>(1, std::min<int64_t>(ns, items / p->p1_blocks));
 }
 
+// Pack the vectors and run the plan's slots (single workgroup or three passes)
+// into its partial sums; returns the number of partial-sum groups.  Phases are
+// timed on `tm` (the plan the caller executes).
 template <typename T>
-void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                 int64_t N, int64_t batch, int64_t ld, hipStream_t s)
+int run_slots(thx_plan *p, thx_plan *tm, const int64_t *off, const int64_t *deg, const double *alpha, int64_t N,
+              int64_t batch, int64_t ld, hipStream_t s)
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
     {
-        PhaseTimer t(p, THX_PHASE_PACK, s);
+        PhaseTimer t(tm, THX_PHASE_PACK, s);
         launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, p->X, p->ncs, s);
     }
     int G = 0;
@@ -888,7 +978,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
             int Gt = (int)std::min<int64_t>(p->S, std::max<int64_t>(1, (p->lds_blocks + batch - 1) / batch));
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
-            PhaseTimer t(p, THX_PHASE_TOEP_LDS, s);
+            PhaseTimer t(tm, THX_PHASE_TOEP_LDS, s);
             if (!launch_toep_lds<T>(p->L, p->lds_radix, p->X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL,
                                     p->Wp, batch, s))
                 throw HipFail{hipErrorInvalidValue};
@@ -898,18 +988,18 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
             for (int s0 = 0; s0 < p->S; s0 += (int)p->U_slots) {
                 const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
                 if (p->fuse_p1 && g.L2 <= 4) {
-                    PhaseTimer t(p, THX_PHASE_ROW, s);
+                    PhaseTimer t(tm, THX_PHASE_ROW, s);
                     if (!launch_mp_p2f<T>(g, p->X, p->ncs, n, ell, s0, ns, p->U, batch, p->that, p->twL1, p->twA,
                                           p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
                 } else {
                     {
-                        PhaseTimer t(p, THX_PHASE_COL_FWD, s);
+                        PhaseTimer t(tm, THX_PHASE_COL_FWD, s);
                         if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch),
                                              nullptr, p->U, batch, p->twL2, p->twA, s))
                             throw HipFail{hipErrorInvalidValue};
                     }
-                    PhaseTimer t(p, THX_PHASE_ROW, s);
+                    PhaseTimer t(tm, THX_PHASE_ROW, s);
                     if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
@@ -918,7 +1008,7 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
                 const int spg = (ns + Gc - 1) / Gc;
                 Gc = (ns + spg - 1) / spg;
                 {
-                    PhaseTimer t(p, THX_PHASE_COL_INV, s);
+                    PhaseTimer t(tm, THX_PHASE_COL_INV, s);
                     if (!launch_mp_p3<T>(g, p->U, p->ncs, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
@@ -929,16 +1019,26 @@ void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const doub
         launch_zero(p->Wp, (int64_t)(p->esize() * (size_t)(batch * p->ncs)), s);
         G = 1;
     }
+    return G;
+}
+
+template <typename T>
+void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                 int64_t N, int64_t batch, int64_t ld, hipStream_t s)
+{
+    const int G = run_slots<T>(p, p, off, deg, alpha, N, batch, ld, s);
+    thx_plan *t = p->tail_on ? p->tail : nullptr;
+    const int G2 = t ? run_slots<float>(t, p, off, deg, alpha, N, batch, ld, s) : 0;
     const double *row0 = nullptr;
     if (p->row0_direct) {
-        PhaseTimer t(p, THX_PHASE_ROW0, s);
+        PhaseTimer tm(p, THX_PHASE_ROW0, s);
         launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0_part, p->row0, s);
         row0 = p->row0;
     }
     {
-        PhaseTimer t(p, THX_PHASE_UNPACK, s);
-        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, p->ncs, p->L, p->alias, p->tsym,
-                         row0, s);
+        PhaseTimer tm(p, THX_PHASE_UNPACK, s);
+        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, t ? t->Wp : nullptr, G2, p->ncs,
+                         p->L, p->alias, p->tsym, row0, s);
     }
     launch_check();
 }
@@ -1137,6 +1237,26 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
             }
         }
         p->p1_blocks = best_p1;
+        // single-precision tail on (with its inverse-pass workgroups) or off
+        // (off: those slots in double precision)
+        if (p->tail) {
+            const int s64 = p->S_full - p->tail->S;
+            p->tail_on = false;
+            p->S = p->S_full;
+            float tb_tail = time_launches(run, s);
+            bool best_on = false;
+            int best_tp3 = p->tail->p3_blocks;
+            p->tail_on = true;
+            p->S = s64;
+            for (int p3 : {512, 1024, 2048}) {
+                p->tail->p3_blocks = p3;
+                const float t = time_launches(run, s);
+                if (t < tb_tail) tb_tail = t, best_on = true, best_tp3 = p3;
+            }
+            p->tail->p3_blocks = best_tp3;
+            p->tail_on = best_on;
+            p->S = best_on ? s64 : p->S_full;
+        }
     }
 }
 
@@ -1443,7 +1563,15 @@ int32_t thx_plan_rank(const thx_plan *p)
 {
     if (!p) return -1;
     int32_t r = 0;
-    for (const thx_plan *q = p; q; q = q->next) r = std::max<int32_t>(r, q->path == 0 ? 0 : q->S);
+    for (const thx_plan *q = p; q; q = q->next) r = std::max<int32_t>(r, q->path == 0 ? 0 : std::max(q->S, q->S_full));
+    return r;
+}
+int32_t thx_plan_tail_slots(const thx_plan *p)
+{
+    if (!p) return -1;
+    int32_t r = 0;
+    for (const thx_plan *q = p; q; q = q->next)
+        if (q->tail && q->tail_on && !p->dense) r += q->tail->S;
     return r;
 }
 int32_t thx_plan_rank_part(const thx_plan *p, int part)

@@ -71,6 +71,7 @@ def _create(lib, kind, params, degree, tol, prec=0, flags=0):
     (0, (), 10, 1.5, 0, 1),
     (0, (), 10, float("nan"), 0, 1),
     (0, (), 10, 1e-15, 7, 1),          # unknown precision
+    (0, (), 10, 1e-15, 3, 1),          # one past THX_FP64_TAIL32
     (2, (), 10, 1e-15, 0, 1),          # ultra2ultra needs two parameters
     (2, (-0.5, 0.5), 10, 1e-15, 0, 1), # lambda must be > 0
     (4, (-1.5, 0.0), 10, 1e-15, 0, 1), # Laguerre parameter must be > -1
@@ -120,6 +121,9 @@ def test_introspection_null_plan(lib):
     lib.thx_plan_fused_columns.restype = ctypes.c_int32
     lib.thx_plan_fused_columns.argtypes = [ctypes.c_void_p]
     assert lib.thx_plan_fused_columns(None) == -1
+    lib.thx_plan_tail_slots.restype = ctypes.c_int32
+    lib.thx_plan_tail_slots.argtypes = [ctypes.c_void_p]
+    assert lib.thx_plan_tail_slots(None) == -1
     lib.thx_plan_enable_timing.restype = ctypes.c_int
     lib.thx_plan_enable_timing.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     assert lib.thx_plan_enable_timing(None, 0xFFFFFFFF) == 1

@@ -1,0 +1,162 @@
+"""GPU parity of THX_FP64_TAIL32 plans (double precision, with the ranks whose
+pivots are below tol * 2^23 of the largest diagonal run in single precision)
+against the oracle.  Bars: the FP64 target, 1e-13 of ||alpha||_1, and for
+leg2cheb the mode's own bound, 3 tol: the truncation bound 2 tol ||alpha||_1
+(D1 = 2/pi, max |T| = sqrt(pi) and max |E| <= tol sqrt(pi) for the Hankel
+residual, Sec. 3 and 2.1) plus at most ~tol/4 from the single-precision ranks.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07486_amd import inputs
+
+from .test_gpu_parity import EPS64, TOL64, _batch_inputs, _dev, _err, thx  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _exec(thx, kind, N, prec, alpha, params=(), tol=EPS64, tune=0):
+    import torch
+    plan = thx.Plan(kind, N, tol, prec, params=params)
+    if tune:
+        plan.autotune(tune)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    return plan, b.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,batch,tune", [(70000, None, 0), (140000, None, 0), (140000, 2, 2), (200001, None, 0)])
+def test_tail32_leg2cheb_full(thx, N, batch, tune):
+    print(f"[case] tail32 leg2cheb N={N} batch={batch} tune={tune}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=N, batch=batch)
+    plan, got = _exec(thx, thx.LEG2CHEB, N, thx.FP64_TAIL32, alpha, tune=tune)
+    _, got64 = _exec(thx, thx.LEG2CHEB, N, thx.FP64, alpha)
+    al = alpha.reshape(-1, N + 1)
+    got, got64 = got.reshape(al.shape), got64.reshape(al.shape)
+    print(f"  K={plan.rank} tail={plan.tail_slots} L={plan.fft_length} path={plan.path}", flush=True)
+    assert plan.path == 2
+    if not tune:
+        assert 0 < plan.tail_slots < plan.rank
+    for j in range(al.shape[0]):
+        ref = oracle.matvec("leg2cheb", al[j])
+        err, err64 = _err(got[j], ref, al[j]), _err(got64[j], ref, al[j])
+        print(f"  vector {j}: err={err:.3e} (all-FP64 plan {err64:.3e})", flush=True)
+        assert np.all(np.isfinite(got[j]))
+        assert err < TOL64 and err < 3 * EPS64
+
+
+def test_tail32_full_size_sampled(thx):
+    N = 1 << 20
+    print(f"[case] tail32 leg2cheb N={N} sampled", flush=True)
+    alpha = inputs.coeffs(N, 1.5, seed=20)
+    plan, got = _exec(thx, thx.LEG2CHEB, N, thx.FP64_TAIL32, alpha)
+    rows = inputs.sample_rows(N, 256, seed=17)
+    ref = oracle.matvec("leg2cheb", alpha, rows=rows)
+    err = float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+    print(f"  K={plan.rank} tail={plan.tail_slots} L={plan.fft_length} sampled err={err:.3e}", flush=True)
+    assert 0 < plan.tail_slots < plan.rank
+    assert np.all(np.isfinite(got))
+    assert err < 3 * EPS64
+
+
+def test_tail32_short_transforms_stay_fp64(thx):
+    # below L = 2^16 no rank moves to single precision unless autotuned: the plan is the FP64 plan,
+    # output for output
+    N = 20000
+    print(f"[case] tail32 leg2cheb N={N} (no tail)", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=3)
+    plan, got = _exec(thx, thx.LEG2CHEB, N, thx.FP64_TAIL32, alpha)
+    _, got64 = _exec(thx, thx.LEG2CHEB, N, thx.FP64, alpha)
+    assert plan.tail_slots == 0
+    assert np.array_equal(got, got64)
+
+
+@pytest.mark.parametrize("kind,params,N,tol", [(1, (), 140000, 1e-17), (2, (1.25, 0.75), 70000, EPS64),
+                                               (4, (0.5, -0.25), 70000, EPS64)])
+def test_tail32_other_kinds(thx, kind, params, N, tol):
+    name = {1: "cheb2leg", 2: "ultra2ultra", 4: "lag2lag"}[kind]
+    print(f"[case] tail32 {name} {params} N={N} tol={tol}", flush=True)
+    alpha = inputs.coeffs(N, 1.5 if kind == 1 else 1.0, seed=N + kind)
+    plan, got = _exec(thx, kind, N, thx.FP64_TAIL32, alpha, params=params, tol=tol)
+    rows = np.unique(np.concatenate([inputs.sample_rows(N, 256, seed=kind), N // 2 - 16 + np.arange(32)]))
+    ref = oracle.matvec(name, alpha, params, rows=rows)
+    err = float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
+    scale = max(1.0, oracle.absmax(name, N, params)) if kind in (2, 4) else 1.0
+    print(f"  K={plan.rank} tail={plan.tail_slots} L={plan.fft_length} sampled err={err:.3e} "
+          f"bar={TOL64 * scale:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < TOL64 * scale
+
+
+def test_tail32_batch_graph(thx):
+    # a mixed batch of long vectors: every bucket with L >= 2^16 carries its own
+    # tail; the graph replay runs the single-precision passes between the FP64
+    # passes and the final step
+    import torch
+    degrees = inputs.batch_degrees(10, 33000, 150000, seed=61)
+    print(f"[case] tail32 batch degrees={degrees.tolist()}", flush=True)
+    flat, parts = _batch_inputs(degrees, 1.0, 62)
+    bt = thx.Batch(thx.LEG2CHEB, degrees, EPS64, thx.FP64_TAIL32)
+    a = _dev(flat)
+    outs = []
+    for graph in (False, True, True):
+        b = torch.full_like(a, float("nan"))
+        bt.execute(a, b, graph=graph)
+        torch.cuda.synchronize()
+        outs.append(b.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    worst = 0.0
+    for i, al in enumerate(parts):
+        o = int(bt.offsets[i])
+        n = len(al) - 1
+        rows = inputs.sample_rows(n, 64, seed=i)
+        ref = oracle.matvec("leg2cheb", al, rows=rows)
+        worst = max(worst, float(np.max(np.abs(outs[0][o:o + n + 1][rows] - ref)) / np.sum(np.abs(al))))
+    print(f"  buckets={bt.buckets()} worst sampled err={worst:.3e}", flush=True)
+    assert worst < 3 * EPS64
+
+
+@pytest.mark.parametrize("log2gain,expect_all", [(60, True), (-60, False)])
+def test_tail32_gain_extremes(thx, monkeypatch, log2gain, expect_all):
+    # every slot in single precision (the double-precision passes then run no slot
+    # and contribute zeros), or none (no tail is built)
+    monkeypatch.setenv("THX_TAIL32_LOG2GAIN", str(log2gain))
+    N = 70000
+    print(f"[case] tail32 leg2cheb N={N} log2 gain={log2gain}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=5)
+    plan, got = _exec(thx, thx.LEG2CHEB, N, thx.FP64_TAIL32, alpha)
+    err = _err(got, oracle.matvec("leg2cheb", alpha), alpha)
+    print(f"  K={plan.rank} tail={plan.tail_slots} err={err:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    if expect_all:
+        assert plan.tail_slots == plan.rank
+        assert err < 5e-6          # the single-precision bar: every rank rounds in FP32
+    else:
+        assert plan.tail_slots == 0
+        assert err < 3 * EPS64
+
+
+def test_tail32_autotuned_short_transforms(thx):
+    # L = 16384 (single-precision columns of 4): the tail is built but off by
+    # default; the autotuner times it for 64 vectors and keeps whichever is faster
+    import torch
+    N, batch = 14000, 64
+    print(f"[case] tail32 leg2cheb N={N} batch={batch} autotuned", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=9, batch=batch)
+    plan = thx.Plan(thx.LEG2CHEB, N, EPS64, thx.FP64_TAIL32)
+    assert plan.fft_length == 16384 and plan.tail_slots == 0
+    plan.autotune(batch)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    plan.execute(a, b)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    worst = max(_err(got[j], oracle.matvec("leg2cheb", alpha[j]), alpha[j]) for j in range(0, batch, 9))
+    print(f"  K={plan.rank} tail={plan.tail_slots} worst err={worst:.3e}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert worst < 3 * EPS64
