@@ -4,7 +4,8 @@
 // (sequence c, element i at logical position i*NB + c).  Each thread keeps
 // E = M*NB/NT complex values in registers.  The transform is a sequence of
 // radix-R stages (R = RMAX while possible, then one stage of 2, 4 or 8, and a
-// radix-3 stage for M = 3 * 2^m); the inverse runs the radices in reverse order.  Between stages the values are
+// radix-3 or radix-5 stage for M = 3 * 2^m or 5 * 2^m); the inverse runs the
+// radices in reverse order.  Between stages the values are
 // exchanged through LDS (padded one slot per 16 to spread the banks); the
 // first stage reads its inputs from registers and the last stage leaves its
 // outputs in registers, so callers load and store global memory directly in
@@ -25,17 +26,19 @@
 
 namespace thx {
 
-// Lengths are M = 2^m or M = 3 * 2^m.  Forward radices of stage s for largest
-// power-of-two radix RMAX (16, 8 or 4): RMAX, RMAX, ..., the power-of-two
-// remainder, then one radix-3 stage when 3 divides M (last forward, first
-// inverse, so the first forward radix stays a power of two).
-constexpr int pow2_part(int M) { return M % 3 == 0 ? M / 3 : M; }
+// Lengths are M = 2^m, 3 * 2^m or 5 * 2^m.  Forward radices of stage s for
+// largest power-of-two radix RMAX (16, 8 or 4): RMAX, RMAX, ..., the
+// power-of-two remainder, then one radix-3 or radix-5 stage when 3 or 5 divides
+// M (last forward, first inverse, so the first forward radix stays a power of
+// two whenever M has a power-of-two factor).
+constexpr int odd_part(int M) { return M % 3 == 0 ? 3 : (M % 5 == 0 ? 5 : 1); }
+constexpr int pow2_part(int M) { return M / odd_part(M); }
 constexpr int nstages2(int P, int RMAX) { return ilog2(P) / ilog2(RMAX) + (ilog2(P) % ilog2(RMAX) ? 1 : 0); }
-constexpr int nstages(int M, int RMAX) { return nstages2(pow2_part(M), RMAX) + (M % 3 == 0 ? 1 : 0); }
+constexpr int nstages(int M, int RMAX) { return nstages2(pow2_part(M), RMAX) + (odd_part(M) > 1 ? 1 : 0); }
 constexpr int fwd_radix(int M, int s, int RMAX)
 {
     const int P = pow2_part(M);
-    return s >= nstages2(P, RMAX) ? 3
+    return s >= nstages2(P, RMAX) ? odd_part(M)
                                   : ((s < ilog2(P) / ilog2(RMAX)) ? RMAX : (1 << (ilog2(P) % ilog2(RMAX))));
 }
 template <bool INV>
@@ -122,6 +125,32 @@ __device__ __forceinline__ void dft3(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2)
     x2 = csub(t, r);
 }
 
+// radix-5 DFT: with c_m = cos(2 pi m / 5), s_m = sin(2 pi m / 5),
+// t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4, t4 = x2 - x3,
+//   y0 = x0 + t1 + t2,
+//   y1,4 = (x0 + c1 t1 + c2 t2) -+ i (s1 t3 + s2 t4),
+//   y2,3 = (x0 + c2 t1 + c1 t2) -+ i (s2 t3 - s1 t4)
+// (forward; the signs of the imaginary terms swap for the inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ void dft5(cpx<T> &x0, cpx<T> &x1, cpx<T> &x2, cpx<T> &x3, cpx<T> &x4)
+{
+    constexpr T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    constexpr T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    const cpx<T> t1 = cadd(x1, x4), t2 = cadd(x2, x3), t3 = csub(x1, x4), t4 = csub(x2, x3);
+    const cpx<T> a1 = {x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y};
+    const cpx<T> a2 = {x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y};
+    const cpx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    const cpx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    // -i b = (b.y, -b.x)
+    const cpx<T> mb1 = INV ? cpx<T>{-b1.y, b1.x} : cpx<T>{b1.y, -b1.x};
+    const cpx<T> mb2 = INV ? cpx<T>{-b2.y, b2.x} : cpx<T>{b2.y, -b2.x};
+    x0 = {x0.x + t1.x + t2.x, x0.y + t1.y + t2.y};
+    x1 = cadd(a1, mb1);
+    x4 = csub(a1, mb1);
+    x2 = cadd(a2, mb2);
+    x3 = csub(a2, mb2);
+}
+
 // Radix-R DFT in registers, R = R1 * R2 with input n = R2 n1 + n2 and output
 // k = k1 + R1 k2: DFT_R1 over n1, twiddle w_R^{n2 k1}, DFT_R2 over n2.
 template <typename T, int R, bool INV>
@@ -130,6 +159,8 @@ __device__ __forceinline__ void dft(cpx<T> *v)
     if constexpr (R == 1) {
     } else if constexpr (R == 3) {
         dft3<T, INV>(v[0], v[1], v[2]);
+    } else if constexpr (R == 5) {
+        dft5<T, INV>(v[0], v[1], v[2], v[3], v[4]);
     } else if constexpr (R == 2) {
         dft2<T, INV>(v[0], v[1]);
     } else if constexpr (R == 4) {
@@ -210,6 +241,7 @@ __device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restri
     if constexpr (R == 4) return;
     const cpx<T> w4 = tw[4 * e1];
     twmul<T, INV>(v[4], w4);
+    if constexpr (R == 5) return;
     twmul<T, INV>(v[5], cmul(w1, w4));
     twmul<T, INV>(v[6], cmul(w2, w4));
     const cpx<T> w7 = cmul(w3, w4);
@@ -234,7 +266,7 @@ struct RegFFT {
     static constexpr int R_LAST = fwd_radix(M, NS - 1, RMAX);
     static constexpr int LDS = lds_padded(M * NB);
     static_assert(E * NT == M * NB, "elements per thread");
-    static_assert(M % 3 != 0 || (M / 3 & (M / 3 - 1)) == 0, "length 2^m or 3 * 2^m");
+    static_assert((pow2_part(M) & (pow2_part(M) - 1)) == 0, "length 2^m, 3 * 2^m or 5 * 2^m");
 
     // logical position (i*NB + c) of register slot `slot` in the forward input layout
     __device__ static __forceinline__ void in_pos(int slot, int &pos, int &c)

@@ -1411,16 +1411,23 @@ __device__ __forceinline__ void xcd_map(int b, int items, int reps, int &item, i
 // 8192 for columns of 512 and more, so that a tile still spans 16 adjacent
 // columns (256-byte segments; one 1024-thread workgroup per CU in 136 KiB of
 // LDS) -- measured 2% faster per execution at L2 = 512, while 32-column tiles
-// at L2 = 256 measured 8% slower than 16.  FP32: 8192 (16384 spilled).
+// at L2 = 256 measured 8% slower than 16.  FP32: 8192 (16384 spilled), except
+// 4096 for columns of 128 and 256 (tiles of 32 and 16 columns, four workgroups
+// per CU instead of two): both column passes 9-10% faster at L2 = 256.
 template <typename T, int L2>
-constexpr int mp_tile() { return sizeof(T) == 4 ? 8192 : (L2 >= 512 ? 8192 : 4096); }
+constexpr int mp_tile()
+{
+    return sizeof(T) == 4 ? ((L2 == 128 || L2 == 256) ? 4096 : 8192) : (L2 >= 512 ? 8192 : 4096);
+}
 constexpr int64_t pow2_floor(int64_t x) { return x < 2 ? 1 : 2 * pow2_floor(x / 2); }
-// Columns of 3 * 2^m (lengths L = 3 * 2^k, which pad mixed batches less) take
-// radix-4 stages and one radix-3 stage with 12 values per thread (6 for columns
-// of 6), so that every radix divides the per-thread count; their tiles are the
-// largest power-of-two number of columns that fits.
-template <int L2> constexpr int col_rmax() { return L2 % 3 == 0 ? 4 : RMAX; }
-template <int L2> constexpr int col_e() { return L2 == 6 ? 6 : 12; }
+// Columns of 3 * 2^m and 5 * 2^m (lengths L = 3 * 2^k and 5 * 2^k, which pad
+// mixed batches less) take radix-4 stages and one radix-3 or radix-5 stage with
+// 12 or 20 values per thread (6 for columns of 6, 10 for columns of 10), so that
+// every radix divides the per-thread count; their tiles are the largest
+// power-of-two number of columns that fits.
+template <int L2> constexpr bool col_mixed() { return L2 % 3 == 0 || L2 % 5 == 0; }
+template <int L2> constexpr int col_rmax() { return col_mixed<L2>() ? 4 : RMAX; }
+template <int L2> constexpr int col_e() { return L2 % 5 == 0 ? (L2 == 10 ? 10 : 20) : (L2 == 6 ? 6 : 12); }
 template <typename T, int L2>
 constexpr int mp_tc()
 {
@@ -1429,16 +1436,22 @@ constexpr int mp_tc()
 template <typename T, int L2>
 constexpr int mp_nt()
 {
-    if constexpr (L2 % 3 == 0) return mp_tc<T, L2>() * L2 / col_e<L2>();
+    if constexpr (col_mixed<L2>()) return mp_tc<T, L2>() * L2 / col_e<L2>();
     else return nthreads<L2, mp_tc<T, L2>()>();
 }
 template <typename T, int L2> using ColFFT = RegFFT<T, L2, mp_tc<T, L2>(), mp_nt<T, L2>(), col_rmax<L2>()>;
 
-// columns the three-pass kernels are built for: 2^m (2 ... 1024) or 3 * 2^m (6 ... 768)
+// columns the three-pass kernels are built for: 2^m (2 ... 1024), 3 * 2^m (6 ... 768)
+// or 5 * 2^m (10 ... 640; a column of 5 would start its inverse with an odd radix,
+// which the inverse pass's split of kept outputs at L2/2 does not handle)
 static bool column_length_ok(int64_t L2)
 {
-    const int64_t P = L2 % 3 == 0 ? L2 / 3 : L2;
-    return (P & (P - 1)) == 0 && (L2 % 3 == 0 ? (L2 >= 6 && L2 <= 768) : (L2 >= 2 && L2 <= 1024));
+    if (L2 < 2) return false;
+    const int64_t q = L2 % 3 == 0 ? 3 : (L2 % 5 == 0 ? 5 : 1), P = L2 / q;
+    if ((P & (P - 1)) != 0) return false;
+    if (q == 3) return L2 >= 6 && L2 <= 768;
+    if (q == 5) return L2 >= 10 && L2 <= 640;
+    return L2 <= 1024;
 }
 
 bool multipass_ok(int64_t L, int64_t L1)
@@ -1456,7 +1469,8 @@ MultiPassGeom multipass_geom(int64_t L, int64_t row)
     if (!ok) row = L / mp_row_short<T>() <= 512 ? mp_row_short<T>() : mp_row_long<T>();
     g.L1 = row;
     g.L2 = L / g.L1;
-    const int64_t tile = sizeof(T) == 4 ? 8192 : (g.L2 >= 512 ? 8192 : 4096); // mp_tile<T, L2>
+    const int64_t tile = sizeof(T) == 4 ? ((g.L2 == 128 || g.L2 == 256) ? 4096 : 8192)
+                                        : (g.L2 >= 512 ? 8192 : 4096); // mp_tile<T, L2>
     g.TC = std::min<int64_t>(64, pow2_floor(tile / g.L2));                    // mp_tc<T, L2>
     return g;
 }
@@ -1739,8 +1753,13 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2f(
     p2_row<T, L1>(v, lds, k2, row, that_perm + (int64_t)k2 * L1, twL1, twA, twL2);
 }
 
+// at least four waves per SIMD for the inverse column pass, two for columns of
+// 5 * 2^m, whose 20 values per thread and 10 accumulators do not fit in 128
+// registers (they spill there)
+template <int L2> constexpr int p3_waves() { return L2 % 5 == 0 ? 2 : 4; }
+
 template <typename T, int L1, int L2>
-__global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_eu(4))) void k_mp_p3(
+__global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_eu(p3_waves<L2>()))) void k_mp_p3(
     const cpx<T> *__restrict__ U, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
     int nslots, int spg, cpx<T> *__restrict__ W, int gofs, int64_t batch,
     const cpx<T> *__restrict__ twL2)
@@ -1817,6 +1836,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
 
 // Column lengths instantiated for each row length (L1 L2 <= MP_LMAX).
 #define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) \
+    X(10) X(20) X(40) X(80) X(160) X(320) X(640) \
     X(6) X(12) X(24) X(48) X(96) X(192) X(384) X(768)
 
 template <typename T, int L1>

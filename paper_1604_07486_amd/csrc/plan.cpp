@@ -266,11 +266,12 @@ void *make_twiddles(thx_plan *p, int64_t M, int64_t count, hipStream_t s, int ke
     return t32;
 }
 
-// Circulant length for a Toeplitz product of n lanes: the smallest 2^k >= 2n - 2,
-// or 3 * 2^(k-2) when that is long enough and the three-pass path takes it with
-// columns of at least 6 entries; the Toeplitz product is exact for any length
-// >= 2n - 2, and the shorter length moves 3/4 of the bytes (members of mixed
-// batches fall in whichever is nearer).  THX_POW2_LENGTHS=1 keeps powers of two.
+// Circulant length for a Toeplitz product of n lanes: the smallest of 2^k,
+// 3 * 2^(k-2) and 5 * 2^(k-3) that is >= 2n - 2, the last two only where the
+// three-pass path takes them (columns of at least 6 or 10 entries); the
+// Toeplitz product is exact for any length >= 2n - 2, and the shorter lengths
+// move 3/4 or 5/8 of the bytes (members of mixed batches fall in whichever is
+// nearest).  THX_POW2_LENGTHS=1 keeps powers of two.
 int64_t fft_length_for(int64_t n, thx_precision prec)
 {
     const int64_t need = std::max<int64_t>(64, 2 * n - 2);
@@ -280,9 +281,12 @@ int64_t fft_length_for(int64_t n, thx_precision prec)
     const bool f64 = prec != THX_FP32_BULK;
     const int64_t lmax = f64 ? lds_max_len<double>() : lds_max_len<float>();
     const int64_t row = f64 ? mp_row_short<double>() : mp_row_short<float>();
-    const int64_t t = p2 / 4 * 3;
-    if (t >= need && t > lmax && t >= 6 * row && t <= MP_LMAX) return t;
-    return p2;
+    int64_t best = p2;
+    for (const int64_t t : {p2 / 4 * 3, p2 / 8 * 5}) {
+        const int64_t min_cols = t % 3 == 0 ? 6 : 10;
+        if (t >= need && t < best && t > lmax && t >= min_cols * row && t <= MP_LMAX) best = t;
+    }
+    return best;
 }
 
 // FFT of the embedded symbol in double precision, natural order, scaled by 1/L.

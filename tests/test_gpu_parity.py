@@ -169,15 +169,20 @@ def test_leg2cheb_lds_radix(thx, N, prec, radix, monkeypatch):
     assert plan.path == 1 and plan.lds_radix == radix
 
 
-# circulant lengths 3 * 2^k (the three-pass path with columns of 3 * 2^m: radix-4
-# stages and one radix-3 stage), both row lengths where the columns allow them,
-# the alias at L = 2n - 2 (N = L), several vectors, other kinds; and the same
-# sizes with power-of-two lengths only (THX_POW2_LENGTHS)
+# circulant lengths 3 * 2^k and 5 * 2^k (the three-pass path with columns of
+# 3 * 2^m or 5 * 2^m: radix-4 stages and one radix-3 or radix-5 stage), both row
+# lengths where the columns allow them, the alias at L = 2n - 2 (N = L), several
+# vectors, other kinds; and the same sizes with power-of-two lengths only
+# (THX_POW2_LENGTHS)
 @pytest.mark.parametrize("N,prec,row,batch,L", [
-    (10000, 0, 2048, 2, 12288), (12288, 0, 0, 1, 12288), (20000, 0, 2048, 1, 24576), (20000, 0, 4096, 3, 24576),
+    (10000, 0, 2048, 2, 12288), (12288, 0, 0, 1, 12288), (22000, 0, 2048, 1, 24576), (22000, 0, 4096, 3, 24576),
     (45000, 0, 4096, 1, 49152), (98304, 0, 2048, 1, 98304), (700000, 0, 0, 1, 786432),
     (20000, 1, 4096, 2, 24576), (45000, 1, 8192, 1, 49152), (45000, 1, 4096, 1, 49152),
     (3 << 20, 0, 0, 1, 3 << 20), (3 << 20, 1, 0, 1, 3 << 20),
+    # 5 * 2^k: columns of 10 ... 640 (the row length falls back to one the columns allow)
+    (20000, 0, 0, 2, 20480), (20480, 0, 0, 1, 20480), (20000, 0, 4096, 1, 20480), (40000, 0, 4096, 1, 40960),
+    (80000, 0, 0, 1, 81920), (300000, 0, 0, 1, 327680), (640000, 0, 0, 1, 655360), (5 << 19, 0, 0, 1, 5 << 19),
+    (40000, 1, 0, 2, 40960), (80000, 1, 8192, 1, 81920), (600000, 1, 0, 1, 655360), (5 << 19, 1, 0, 1, 5 << 19),
 ])
 def test_leg2cheb_three_times_pow2_lengths(thx, N, prec, row, batch, L, monkeypatch):
     if row:
@@ -198,9 +203,12 @@ def test_leg2cheb_three_times_pow2_lengths(thx, N, prec, row, batch, L, monkeypa
 
 
 @pytest.mark.parametrize("kind,params,N,L", [
-    (4, (0.5, -0.25), 10000, 24576),   # Laguerre: n = N + 1 lanes, two ranks per complex slot
-    (1, (), 20000, 24576),             # cheb2leg: row 0 direct
-    (2, (0.75, 0.25), 40000, 49152),   # ultraspherical, case 2
+    (4, (0.5, -0.25), 11000, 24576),   # Laguerre: n = N + 1 lanes, two ranks per complex slot
+    (1, (), 22000, 24576),             # cheb2leg: row 0 direct
+    (2, (0.75, 0.25), 42000, 49152),   # ultraspherical, case 2
+    (4, (0.5, -0.25), 10000, 20480),   # the same kinds at lengths 5 * 2^k
+    (1, (), 20000, 20480),
+    (2, (0.75, 0.25), 40000, 40960),
 ])
 def test_three_times_pow2_lengths_other_kinds(thx, kind, params, N, L):
     plan, _ = _check_full(thx, kind, N, thx.FP64, params, flags=thx.FLAG_FORCE_FFT, seed=N,
