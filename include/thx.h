@@ -120,7 +120,10 @@ thx_status thx_plan_destroy(thx_plan *plan);
 /* Plan introspection (host values; no device work).
  * rank: number of FFT slots K (for parity-split kinds max(K_even, K_odd)).
  * rank_part: rank of Hankel part `part` (0 = even / only, 1 = odd), -1 if absent.
- * fft_length: circulant-embedding length L (0 on the direct path).
+ * fft_length: circulant-embedding length L (0 on the direct path): the smallest
+ * of 2^k, 3 * 2^(k-2) and 5 * 2^(k-3) that is >= 2n - 2 for n Toeplitz lanes
+ * (Sec. 2: any length >= 2n - 2 embeds the product exactly), the last two only
+ * on the three-pass path with columns of at least 6 / 10 entries.
  * path: 0 direct (entries generated per output row), 1 single-workgroup LDS
  * FFT, 2 three-pass FFT, 3 dense: below the FFT crossover (degree + 1 <= 512,
  * THX_FLAG_NO_DENSE not set) the plan materialises the (degree+1)^2 matrix once
