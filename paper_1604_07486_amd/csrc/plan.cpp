@@ -1368,10 +1368,19 @@ struct thx_batch {
         thx_plan *plan = nullptr;
         int64_t members = 0, Nmax = 0, L = 0;
         int64_t *d_off = nullptr, *d_deg = nullptr;
+        int lane = 0; // 0: the caller's (or capture) stream, 1: side_stream
     };
     int64_t count = 0, total = 0;
     std::vector<Bucket> buckets;
     hipStream_t cap_stream = nullptr;
+    // Buckets read and write disjoint coefficients, so the FFT buckets run in two
+    // lanes: one bucket's launch ramps and short single-workgroup transforms
+    // overlap another's HBM-bound passes (the dense product and the unit step stay
+    // in the first lane: overlapped with each other they measured slower).  The
+    // side lane forks from and joins the calling stream through events, also under
+    // capture (the graph then has two branches).
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *g_alpha = nullptr;
     double *g_beta = nullptr;
@@ -1379,6 +1388,9 @@ struct thx_batch {
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (side_stream) (void)hipStreamDestroy(side_stream);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         for (auto &b : buckets) {
             delete b.plan;
             dfree(b.d_off);
@@ -1390,6 +1402,45 @@ struct thx_batch {
 namespace {
 
 constexpr int64_t MAX_BUCKET_MEMBERS = 65535; // grid.y limit of the per-vector launches
+
+// Rough cost of one execution of a bucket, to balance the two lanes: FFT work
+// ~ members L K, the dense product ~ members (N+1)^2 on the matrix cores, the
+// direct evaluation ~ members (N+1)^2 on the vector units, a unit step ~ members
+// (N+1).
+double bucket_cost(const thx_batch::Bucket &bk)
+{
+    const double n1 = (double)bk.Nmax + 1, m = (double)bk.members;
+    const thx_plan *p = bk.plan;
+    if (p->dense) return m * n1 * n1 / 64;
+    if (p->path == 0) return m * n1 * n1 / 8;
+    if (p->path == 4) return 3 * m * n1;
+    return m * (double)p->L * std::max(1, std::max(p->S, p->S_full));
+}
+
+bool bucket_is_fft(const thx_batch::Bucket &bk)
+{
+    return !bk.plan->dense && (bk.plan->path == 1 || bk.plan->path == 2);
+}
+
+// Longest-first assignment of the FFT buckets to the lane with less work so far
+// (the others stay in lane 0, counted there); the launch order within a lane
+// stays the bucket order.
+void assign_lanes(thx_batch *b)
+{
+    std::vector<size_t> order;
+    double load[2] = {0, 0};
+    for (size_t i = 0; i < b->buckets.size(); ++i) {
+        if (bucket_is_fft(b->buckets[i])) order.push_back(i);
+        else load[0] += bucket_cost(b->buckets[i]);
+    }
+    std::sort(order.begin(), order.end(),
+              [&](size_t x, size_t y) { return bucket_cost(b->buckets[x]) > bucket_cost(b->buckets[y]); });
+    for (size_t i : order) {
+        const int lane = load[1] < load[0] ? 1 : 0;
+        b->buckets[i].lane = lane;
+        load[lane] += bucket_cost(b->buckets[i]);
+    }
+}
 
 thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, int nparams, const int64_t *degrees,
                         int64_t count, double tol, thx_precision prec, uint32_t flags, hipStream_t s)
@@ -1477,6 +1528,14 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
             }
         }
         hip_check(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        int fft_buckets = 0;
+        for (const auto &bk : b->buckets) fft_buckets += bucket_is_fft(bk) ? 1 : 0;
+        if (fft_buckets > 1) {
+            hip_check(hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking));
+            hip_check(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+            hip_check(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+            assign_lanes(b);
+        }
     } catch (const HipFail &e) {
         g_last_hip_error = (int)e.e;
         delete b;
@@ -1491,8 +1550,18 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
 
 void batch_launch(thx_batch *b, const double *alpha, double *beta, hipStream_t s)
 {
+    if (!b->side_stream) {
+        for (auto &bk : b->buckets)
+            execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0, s, b->total);
+        return;
+    }
+    hip_check(hipEventRecord(b->ev_fork, s));
+    hip_check(hipStreamWaitEvent(b->side_stream, b->ev_fork, 0));
     for (auto &bk : b->buckets)
-        execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0, s, b->total);
+        execute_core(bk.plan, bk.d_off, bk.d_deg, alpha, beta, bk.Nmax, bk.members, 0,
+                     bk.lane ? b->side_stream : s, b->total);
+    hip_check(hipEventRecord(b->ev_join, b->side_stream));
+    hip_check(hipStreamWaitEvent(s, b->ev_join, 0));
 }
 
 thx_status batch_execute(thx_batch *b, const double *alpha, double *beta, int use_graph, hipStream_t s)
