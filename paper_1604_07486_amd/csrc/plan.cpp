@@ -1281,8 +1281,8 @@ thx_status autotune(thx_plan *p, int64_t batch, hipStream_t s)
             if (q->path == 0 || p->N < 2) continue;
             ensure_workspace(q, fb);
             const auto t0 = std::chrono::steady_clock::now();
-            for (int it = 0; it < 256; it += 4) {
-                for (int r = 0; r < 4; ++r) execute_stage(q, nullptr, nullptr, a, b, q->N, fb, q->N + 1, s);
+            for (int it = 0; it < 256; ++it) {
+                execute_stage(q, nullptr, nullptr, a, b, q->N, fb, q->N + 1, s);
                 hip_check(hipStreamSynchronize(s));
                 if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(15)) break;
             }
