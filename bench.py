@@ -55,6 +55,8 @@ def parse():
 
 
 COPY_BYTES = 512 << 20
+MFMA_FP64_TFLOPS = 78.6   # MI355X dense matrix-core peaks
+MFMA_BF16_TFLOPS = 2500.0
 
 # Measured HBM traffic of the dominant kernel (row pass of the headline plan),
 # valid only for the device sources it was taken with, the same template
@@ -335,6 +337,34 @@ def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bul
     return batch_res
 
 
+def dense_alone(thx, torch, a5, b5, prec, tolh, params, steps):
+    """The 65536 degree-255 members alone through one dense plan (matrix cores): time per
+    product, useful flops (the upper triangle: (n+1)(n+2)/2 multiply-adds per vector) against
+    the matrix-core peak the form runs on, and alpha + beta bytes against HBM."""
+    n, m = 255, 65536
+    plan = thx.Plan(thx.ULTRA2ULTRA, n, tolh, prec, params=params)
+    if plan.path != 3:
+        return None
+    a = a5[:m * (n + 1)].view(m, n + 1)
+    b = b5[:m * (n + 1)].view(m, n + 1)
+    for _ in range(3):
+        plan.execute(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(10, steps)
+    e0.record()
+    for _ in range(reps):
+        plan.execute(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = m * (n + 1) * (n + 2)
+    # FP64 matrix cores; the split-bfloat16 form issues eight bfloat16 products per useful one
+    peak = MFMA_FP64_TFLOPS if prec == thx.FP64 else MFMA_BF16_TFLOPS / 8
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"ms": round(ms, 4), "useful_tflops": round(tf, 2), "peak_tflops": peak,
+            "frac_of_peak": round(tf / peak, 4), "hbm_gbs": round(2 * m * (n + 1) * 8 / (ms * 1e-3) / 1e9, 1)}
+
+
 def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2cheb"),
                 precs=("fp64", "fp32_bulk")):
     """65536 x degree 255 + 64 x degree 2^18 in one batch, ultraspherical and Jacobi."""
@@ -384,6 +414,8 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
                                          "ms_per_batch": round(ms5, 4), "buckets": bt.buckets(),
                                          "max_err_over_l1_sampled": worst}
             del bt
+            if short == "ultra":
+                conf5[f"dense_alone_{pname}"] = dense_alone(thx, torch, a5, b5, prec, tolh, params, steps)
     conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
                          "N(0,1)(k+1)^-1 seed 55, hipGraph replay, buckets autotuned; ultraspherical errors "
                          "divided by the entry growth 2N+1; Jacobi checked on the degree-255 members")
