@@ -431,7 +431,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this library runs on a single GPU; --gpus must be 1 "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
