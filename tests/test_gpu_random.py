@@ -2,8 +2,9 @@
 and the plan's path choices (forced FFT, autotuning, row length, FFT radix,
 slot grouping, fused column pass) drawn together, so that combinations the
 targeted tests do not list are compared with the oracle too.  Same bars as
-test_gpu_parity: 1e-13 (FP64) and 5e-6 (FP32-bulk) of ||alpha||_1, scaled by
-the largest matrix entry where entries grow with the degree.
+test_gpu_parity: 1e-13 (FP64, and FP64 with the single-precision tail) and 5e-6
+(FP32-bulk) of ||alpha||_1, scaled by the largest matrix entry where entries grow
+with the degree.
 """
 from __future__ import annotations
 
@@ -17,7 +18,7 @@ from .test_gpu_parity import _dev, _err, _jac_ref, thx  # noqa: F401  (thx: the 
 
 pytestmark = pytest.mark.gpu
 
-CASES = 48
+CASES = 64
 
 
 def _case(i):
@@ -25,12 +26,12 @@ def _case(i):
     kind = int(g.integers(0, 7))
     N = int(np.exp(g.uniform(np.log(2), np.log(25000))))
     batch = int(g.integers(1, 3))
-    prec = int(g.integers(0, 2))
+    prec = int(g.integers(0, 3))   # FP64, FP32-bulk, FP64 with the single-precision tail
     force_fft = bool(g.integers(0, 2))
     tune = bool(g.integers(0, 2))
     env = {}
     if g.uniform() < 0.4:
-        env["THX_ROW_LEN"] = str([2048, 4096][int(g.integers(0, 2))] * (1 if prec == 0 else 2))
+        env["THX_ROW_LEN"] = str([2048, 4096][int(g.integers(0, 2))] * (2 if prec == 1 else 1))
     r = g.uniform()
     if r < 0.25:
         env["THX_P1_BLOCKS"] = "1"
@@ -85,12 +86,13 @@ def test_random_case(thx, i, monkeypatch):
     # Hankel tolerances: D1 and D2 of cheb2leg and of the Jacobi stages amplify the
     # truncation error (up to ~1e3 of tol for these parameter ranges, measured), so
     # their parts are factorised further, as a caller of those kinds would
+    fp64 = prec != 1
     if kind == 1:
-        tol = 1e-17 if prec == 0 else 1e-9
+        tol = 1e-17 if fp64 else 1e-9
     elif kind in (3, 5, 6):
-        tol = 1e-16 if prec == 0 else 1e-10
+        tol = 1e-16 if fp64 else 1e-10
     else:
-        tol = 1e-15 if prec == 0 else 1e-7
+        tol = 1e-15 if fp64 else 1e-7
     alpha = inputs.coeffs(N, p, seed=100 + i, batch=batch)
     plan = thx.Plan(kind, N, tol, prec, params=params, flags=thx.FLAG_FORCE_FFT if force_fft else 0)
     if tune:
@@ -100,7 +102,7 @@ def test_random_case(thx, i, monkeypatch):
     plan.execute(a, b)
     torch.cuda.synchronize()
     got = b.cpu().numpy()
-    bar = 1e-13 if prec == 0 else 5e-6
+    bar = 1e-13 if fp64 else 5e-6
     if kind in (3, 5, 6):
         scale = _jac_scale(kind, N, params)
     elif kind in (2, 4):
@@ -115,7 +117,7 @@ def test_random_case(thx, i, monkeypatch):
             ref = oracle.matvec({0: "leg2cheb", 1: "cheb2leg", 2: "ultra2ultra", 4: "lag2lag"}[kind], alpha[j],
                                 params)
         err = _err(got[j], ref, alpha[j])
-        print(f"  vector {j}: path={plan.path} K={plan.rank} L={plan.fft_length} err={err:.3e} "
-              f"bar={bar * scale:.3e}", flush=True)
+        print(f"  vector {j}: path={plan.path} K={plan.rank} tail={plan.tail_slots} L={plan.fft_length} "
+              f"err={err:.3e} bar={bar * scale:.3e}", flush=True)
         assert np.all(np.isfinite(got[j]))
         assert err < bar * scale, (i, j, err)
