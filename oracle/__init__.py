@@ -15,6 +15,11 @@ Contents
   Sec. 5.3 describes: a change of the second parameter through the reflection
   P_k^{(a,b)}(-x) = (-1)^k P_k^{(b,a)}(x), then a change of the first one, and
   for Chebyshev targets the normalisation T_k = P_k^{(-1/2,-1/2)}/P_k^{(-1/2,-1/2)}(1).
+* ``jacobi_step`` / ``jac2jac_rows`` / ``jac2cheb_rows`` -- the whole-number
+  change of the first Jacobi parameter (Sec. 5.3, case 1) by its bidiagonal
+  factor in O(N), and a sampled-row Jacobi conversion that takes that step first
+  (the expansion in the target basis is unique, so the order of the steps does
+  not change the result): the reference for long vectors.
 * ``pivoted_cholesky`` -- the O(K^2 N) pivoted Cholesky of Sec. 2.1 (Fig. 3),
   in numpy float64, used to check the GPU factorisation's invariants.
 
@@ -68,6 +73,8 @@ def _load():
         lib.orc_lambda.restype = ctypes.c_int
         lib.orc_lambda_str.argtypes = [i64, ctypes.c_char_p, ctypes.c_int]
         lib.orc_lambda_str.restype = ctypes.c_int
+        lib.orc_jacobi_step.argtypes = [ctypes.c_double, ctypes.c_double, i64, dp, dp, ctypes.c_int]
+        lib.orc_jacobi_step.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -176,6 +183,54 @@ def cheb2jac(alpha, g: float, d: float) -> np.ndarray:
     """Coefficients in P^{(g,d)} of sum_k alpha_k T_k: T_k = P_k^{(-1/2,-1/2)} / P_k^{(-1/2,-1/2)}(1)."""
     x = np.ascontiguousarray(alpha, dtype=np.float64)
     return jac2jac(x / cheb_norm(x.shape[0] - 1), -0.5, -0.5, g, d)
+
+
+def jacobi_step(alpha, a: float, b: float, up: bool) -> np.ndarray:
+    """Coefficients in P^(a+1,b) (up) or P^(a-1,b) (down) of sum_k alpha_k P_k^(a,b).
+
+    Sec. 5.3, case 1: the upper-bidiagonal factor S_(a,b) of the textbook
+    connection relation, applied directly for a rise and by backward
+    substitution for a drop; O(N) in binary128 (``orc_jacobi_step``).
+    """
+    x = np.ascontiguousarray(alpha, dtype=np.float64)
+    out = np.empty_like(x)
+    rc = _load().orc_jacobi_step(float(a), float(b), x.shape[0] - 1, _dptr(x), _dptr(out), 1 if up else -1)
+    if rc != 0:
+        raise ValueError(f"orc_jacobi_step failed (rc={rc}) for a={a} b={b}")
+    return out
+
+
+def jac2jac_rows(alpha, a: float, b: float, g: float, d: float, rows) -> np.ndarray:
+    """Rows ``rows`` of the coefficients in P^(g,d) of sum_k alpha_k P_k^(a,b), a - g whole.
+
+    The first parameter moves a -> g in unit steps (Sec. 5.3, case 1, O(N) per
+    step), then the second b -> d through the reflection of Sec. 5.3 with the
+    case-2 closed form evaluated on the requested rows only.  Sec. 5.3 takes the
+    other order (second parameter first); the expansion is unique, so both
+    orders give the same coefficients.
+    """
+    x = np.ascontiguousarray(alpha, dtype=np.float64)
+    steps = g - a
+    if steps != round(steps):
+        raise ValueError("jac2jac_rows needs a whole-number change of the first parameter")
+    cur = a
+    for _ in range(int(abs(round(steps)))):
+        up = g > cur
+        x = jacobi_step(x, cur, b, up)
+        cur = cur + 1.0 if up else cur - 1.0
+    rows = np.asarray(rows, dtype=np.int64)
+    if b == d:
+        return x[rows]
+    sgn = np.where(np.arange(x.shape[0]) % 2 == 0, 1.0, -1.0)
+    y = matvec("jac2jac_b", sgn * x, (b, g, d), rows=rows)
+    return np.where(rows % 2 == 0, 1.0, -1.0) * y
+
+
+def jac2cheb_rows(alpha, a: float, b: float, rows) -> np.ndarray:
+    """Rows ``rows`` of the Chebyshev coefficients of sum_k alpha_k P_k^(a,b), a + 1/2 whole."""
+    rows = np.asarray(rows, dtype=np.int64)
+    y = jac2jac_rows(alpha, a, b, -0.5, -0.5, rows)
+    return y * cheb_norm(np.asarray(alpha).shape[0] - 1)[rows]
 
 
 # --------------------------------------------------------------------------

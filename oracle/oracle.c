@@ -20,6 +20,7 @@
  *   2 ultra2ultra Sec. 5.2, eq. (UltraSconversion), params (lambda1, lambda2)
  *   3 jac2jac    Sec. 5.3, case-2 closed form (beta = delta), params (a, b, g)
  *   4 lag2lag    Sec. 5.4, NIST 18.18.18 closed form, params (a1, a2)
+ * plus the unit steps of the Jacobi case 1 (orc_jacobi_step), O(N).
  *
  * Readings of the paper taken here (each pinned by tests/test_oracle_pins.py):
  *   - eq. (M), first case: the condition "j even" at j = 0 is read as "k even"
@@ -290,33 +291,46 @@ static int ctx_init(orc_ctx *C, int kind, const double *params, int64_t N)
     return -1;
 }
 
-/* Jacobi row, Sec. 5.3 case-2 closed form (beta = delta) written with
+/* Jacobi entry, Sec. 5.3 case-2 closed form (beta = delta) written with
  * Pochhammer symbols so that every factor stays finite:
  *   A_jk = D_j (e+k)_j/(b+1)_j (b+1)_k/(c+1)_{k+j} (a-g)_{k-j}/(k-j)!,
  *   c = g+b+1, e = a+b+1, D_j = (2j+c)(c+1)_{j-1} (j > 0), D_0 = 1.
- * Magnitudes are combined in log space (binary128) before one exp. */
-static double row_jacobi(const orc_ctx *C, int64_t j, const double *alpha)
+ * Magnitudes are combined in log space (binary128) before one exp.  lgD is
+ * log|D_j| (jacobi_lgD).  Sets *zero when the entry vanishes. */
+static f128 jacobi_lgD(const orc_ctx *C, int64_t j)
 {
     f128 c = (f128)C->p[2] + (f128)C->p[1] + 1;
-    f128 lgD = 0;
-    if (j > 0) lgD = logq(fabsq(2 * (f128)j + c)) + C->jb_logC[j - 1];
+    return j > 0 ? logq(fabsq(2 * (f128)j + c)) + C->jb_logC[j - 1] : 0;
+}
+
+static ldbl jacobi_entry(const orc_ctx *C, int64_t j, int64_t k, f128 lgD, int *zero)
+{
+    int64_t sidx = k + j;
+    f128 lg;
+    int sg;
+    *zero = 0;
+    if (C->jb_zeroE[k]) {
+        int z;
+        lg = log_poch((f128)C->p[0] + (f128)C->p[1] + 1 + (f128)k, j, &sg, &z);
+        if (z) { *zero = 1; return 0; }
+    } else {
+        if (C->jb_zeroE[sidx]) { *zero = 1; return 0; }
+        lg = C->jb_logE[sidx] - C->jb_logE[k];
+        sg = C->jb_sgnE[sidx] * C->jb_sgnE[k];
+    }
+    lg += C->jb_logB[k] - C->jb_logB[j] - C->jb_logC[sidx] + lgD;
+    return (ldbl)sg * C->jb_D[j] * expl((ldbl)lg) * C->pt[k - j];
+}
+
+static double row_jacobi(const orc_ctx *C, int64_t j, const double *alpha)
+{
+    const f128 lgD = jacobi_lgD(C, j);
     ldbl s = 0, cc = 0;
     for (int64_t k = j; k <= C->N; ++k) {
         if (alpha[k] == 0.0) continue;
-        int64_t sidx = k + j;
-        f128 lg;
-        int sg;
-        if (C->jb_zeroE[k]) {
-            int z;
-            lg = log_poch((f128)C->p[0] + (f128)C->p[1] + 1 + (f128)k, j, &sg, &z);
-            if (z) continue;
-        } else {
-            if (C->jb_zeroE[sidx]) continue;
-            lg = C->jb_logE[sidx] - C->jb_logE[k];
-            sg = C->jb_sgnE[sidx] * C->jb_sgnE[k];
-        }
-        lg += C->jb_logB[k] - C->jb_logB[j] - C->jb_logC[sidx] + lgD;
-        ldbl a = (ldbl)sg * C->jb_D[j] * expl((ldbl)lg) * C->pt[k - j];
+        int z;
+        ldbl a = jacobi_entry(C, j, k, lgD, &z);
+        if (z) continue;
         neumaier_add(&s, &cc, a * (ldbl)alpha[k]);
     }
     return (double)(s + cc);
@@ -381,30 +395,55 @@ double orc_absmax(int kind, const double *params, int64_t N)
     orc_ctx C;
     if (N < 0 || ctx_init(&C, kind, params, N)) return -1.0;
     double best = 0.0;
-    double *e = (kind == ORC_JAC2JAC) ? (double *)calloc((size_t)(N + 1), sizeof(double)) : NULL;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : best)
     for (int64_t j = 0; j <= N; ++j) {
+        const f128 lgD = kind == ORC_JAC2JAC ? jacobi_lgD(&C, j) : 0;
         for (int64_t k = j; k <= N; ++k) {
             double v;
-            if (kind == ORC_JAC2JAC) continue;
-            v = fabs((double)entry(&C, j, k));
+            if (kind == ORC_JAC2JAC) {
+                int z;
+                v = fabs((double)jacobi_entry(&C, j, k, lgD, &z));
+            } else {
+                v = fabs((double)entry(&C, j, k));
+            }
             if (v > best) best = v;
         }
     }
-    if (kind == ORC_JAC2JAC) {
-        /* Jacobi entries come from row_jacobi with unit vectors (small N only) */
-        for (int64_t k = 0; k <= N; ++k) {
-            e[k] = 1.0;
-            for (int64_t j = 0; j <= k; ++j) {
-                double v = fabs(row_jacobi(&C, j, e));
-                if (v > best) best = v;
-            }
-            e[k] = 0.0;
-        }
-        free(e);
-    }
     ctx_free(&C);
     return best;
+}
+
+/* Jacobi case 1 of Sec. 5.3 (a whole-number change of the first parameter),
+ * one unit step in O(N), binary128.  The step up is the upper-bidiagonal factor
+ * S_(a,b) that maps coefficients in P^(a,b) to coefficients in P^(a+1,b); its
+ * entries come from the textbook connection relation (a consequence of the
+ * three-term recurrence, DLMF 18.9.5 with the reflection of Tab. 18.6.1)
+ *   (2n+a+b+1) P_n^(a,b) = (n+a+b+1) P_n^(a+1,b) - (n+b) P_{n-1}^(a+1,b):
+ *   S_nn = (n+a+b+1)/(2n+a+b+1),  S_{n,n+1} = -(n+b+1)/(2n+a+b+3)
+ * (the factor printed in the paper carries a+1, a+2, ... in the second
+ * diagonal; the relation above, checked against exact bases, has b+1, b+2, ...).
+ * dir = +1: out = S_(a,b) alpha (the result is in P^(a+1,b));
+ * dir = -1: out solves S_(a-1,b) out = alpha by backward substitution, as the
+ * paper prescribes for a decrease (the result is in P^(a-1,b)).
+ * S_00 = 1 also when a+b+1 = 0 (the n = 0 limit).  Returns 0 on success. */
+int orc_jacobi_step(double a_, double b_, int64_t N, const double *alpha, double *out, int dir)
+{
+    if (N < 0 || !alpha || !out || (dir != 1 && dir != -1)) return -1;
+    const f128 b = b_, a = dir == 1 ? (f128)a_ : (f128)a_ - 1;  /* the factor S_(a,b) */
+    if (!(a > -1) || !(b > -1)) return -1;
+    f128 *x = (f128 *)malloc(sizeof(f128) * (size_t)(N + 2));
+    if (!x) return -2;
+    x[N + 1] = 0;
+    for (int64_t n = N; n >= 0; --n) {
+        const f128 fn = (f128)n;
+        const f128 dnn = n == 0 ? (f128)1 : (fn + a + b + 1) / (2 * fn + a + b + 1);
+        const f128 up = -(fn + b + 1) / (2 * fn + a + b + 3);
+        if (dir == 1) x[n] = dnn * (f128)alpha[n] + (n < N ? up * (f128)alpha[n + 1] : 0);
+        else x[n] = ((f128)alpha[n] - up * x[n + 1]) / dnn;
+    }
+    for (int64_t n = 0; n <= N; ++n) out[n] = (double)x[n];
+    free(x);
+    return 0;
 }
 
 /* Lambda(n) = Gamma(n+1/2)/Gamma(n+1), n = 0..M, rounded to double. */

@@ -158,6 +158,51 @@ def test_cheb2jac_exact():
         assert np.max(np.abs(oracle.cheb2jac(e, float(g), float(d)) - Af[:, k])) < 1e-13 * max(1.0, np.abs(Af).max())
 
 
+@pytest.mark.parametrize("a,b", [(F(1, 2), F(-1, 4)), (F(-1, 2), F(-1, 4)), (F(1, 3), F(2, 5)),
+                                 (F(-1, 4), F(-3, 4)), (F(3, 2), F(0))])
+@pytest.mark.parametrize("up", [True, False])
+def test_jacobi_step_exact(a, b, up):
+    # Sec. 5.3 case 1: one whole-number step of the first parameter, against the
+    # exact conversion matrix of the textbook bases (the step down exercises the
+    # backward substitution)
+    g = a + 1 if up else a - 1
+    if not g > -1:
+        pytest.skip("target parameter must stay above -1")
+    A = _exact_float(eb.conversion(eb.basis("jacobi", N_EXACT, (a, b)),
+                                   eb.basis("jacobi", N_EXACT, (g, b)), N_EXACT))
+    for k in range(N_EXACT + 1):
+        e = np.zeros(N_EXACT + 1)
+        e[k] = 1.0
+        col = oracle.jacobi_step(e, float(a), float(b), up)
+        assert np.max(np.abs(col - A[:, k])) < 1e-15 * max(1.0, np.max(np.abs(A[:, k]))), k
+
+
+def test_jac2cheb_rows_exact():
+    # the sampled-row route (unit steps of the first parameter, then the
+    # reflected second-parameter stage on the requested rows) against exact bases
+    a, b = F(1, 2), F(-1, 4)
+    N = 12
+    A = _exact_float(eb.conversion(eb.basis("jacobi", N, (a, b)), eb.basis("cheb", N), N))
+    rows = np.array([0, 1, 5, 11, 12])
+    for k in range(N + 1):
+        e = np.zeros(N + 1)
+        e[k] = 1.0
+        assert np.max(np.abs(oracle.jac2cheb_rows(e, float(a), float(b), rows) - A[rows, k])) < 1e-14
+
+
+@pytest.mark.parametrize("a,b,g,d", [(0.5, -0.25, -0.5, -0.5), (1.5, 0.2, -0.5, 0.7), (-0.5, 0.3, 1.5, 0.3)])
+def test_jac2jac_rows_matches_full_route(a, b, g, d):
+    # the two oracle routes (Sec. 5.3 order, and unit steps first) give the same
+    # expansion on a few hundred coefficients
+    N = 700
+    alpha = inputs.coeffs(N, 1.0, seed=29)
+    rows = inputs.sample_rows(N, 50, seed=30)
+    full = oracle.jac2jac(alpha, a, b, g, d)
+    got = oracle.jac2jac_rows(alpha, a, b, g, d, rows)
+    scale = max(1.0, float(np.max(np.abs(full))))
+    assert np.max(np.abs(got - full[rows])) < 1e-14 * scale * np.sum(np.abs(alpha))
+
+
 @pytest.mark.parametrize("a1,a2", [(F(1, 2), F(-1, 4)), (F(0), F(1, 2)), (F(3, 2), F(0))])
 def test_laguerre_exact(a1, a2):
     A = eb.conversion(eb.basis("laguerre", N_EXACT, (a1,)), eb.basis("laguerre", N_EXACT, (a2,)), N_EXACT)
@@ -187,7 +232,8 @@ def test_polynomial_identity(kind, src, dst, params, N):
 
 
 @pytest.mark.parametrize("kind,params", [("leg2cheb", ()), ("cheb2leg", ()), ("ultra2ultra", (1.5, 0.5)),
-                                         ("jac2jac_b", (0.5, -0.25, -0.5)), ("lag2lag", (0.5, -0.25))])
+                                         ("jac2jac_b", (0.5, -0.25, -0.5)), ("jac2jac_b", (-0.25, 0.5, -0.5)),
+                                         ("lag2lag", (0.5, -0.25))])
 def test_absmax_matches_dense(kind, params):
     N = 37
     assert oracle.absmax(kind, N, params) == np.max(np.abs(oracle.dense(kind, N, params)))
