@@ -35,8 +35,9 @@ typedef enum {
     THX_OK = 0,
     THX_INVALID_ARGUMENT = 1, /* bad size, parameter, tolerance or null pointer   */
     THX_UNSUPPORTED = 2,      /* parameters outside the implemented cases         */
-    THX_TOL_NOT_REACHED = 3,  /* pivoted Cholesky hit its rank cap before tol;
-                                 the plan is still created and usable            */
+    THX_TOL_NOT_REACHED = 3,  /* pivoted Cholesky hit its rank cap before tol, or
+                                 tol is below the double-precision floor; the
+                                 plan is still created and usable                 */
     THX_OUT_OF_MEMORY = 4,    /* device or host allocation failed                  */
     THX_HIP_ERROR = 5         /* a HIP runtime call failed                         */
 } thx_status;
@@ -81,25 +82,38 @@ typedef struct thx_plan thx_plan;
 
 /* Plan for converting polynomials of degree <= `degree` (Fig. 1 steps 1-2 and the
  * symbol FFT): fills the Lambda / Gamma-ratio tables, runs the pivoted Cholesky
- * of the Hankel part(s) to relative tolerance `tol` (stop when the largest
- * residual diagonal entry is <= tol * max diag(H); Sec. 2.1 leaves the rule
- * open), and transforms the Toeplitz symbol.  The plan may be reused for any
- * number of executions (Sec. 2.1, last paragraph).
+ * of the Hankel part(s) (Sec. 2.1, Fig. 3), and transforms the Toeplitz symbol.
+ * The plan may be reused for any number of executions (Sec. 2.1, last paragraph).
+ *   tol: the same target for every kind.  Sec. 2.1 leaves the stopping rule
+ *   open; here pivots are chosen on, and the factorisation stopped by, the
+ *   residual diagonal d_j weighted by w_j = |D1_j D2_j| (the diagonal pivoting of
+ *   S H S with S = diag(sqrt w)), until max_j w_j d_j <= eps max_j w_j H_jj with
+ *   eps = 2 tol |t_0| / (amp max_m |t_m|), amp = max_{j <= k} r_j / r_k,
+ *   r = sqrt|D1 / D2|.  The truncation then changes beta by at most
+ *   2 tol max_j |A_jj| ||alpha||_1, whatever D1 and D2 amplify (for leg2cheb,
+ *   max_j |A_jj| = 1 and the rule is "largest residual diagonal <= tol max diag(H)").
+ *   eps is never taken below 2^-51 (the double-precision noise of the residual);
+ *   a tol that would need less returns THX_TOL_NOT_REACHED with a usable plan.
+ *   Multi-stage conversions factorise every stage to the same tol.
  *   params / nparams: kind parameters -- ULTRA2ULTRA (l1, l2) with l1, l2 > 0
  *   (Sec. 5.2: one stage when l1 - l2 <= 1, negative integer differences
  *   banded (case 1); a larger drop goes down in unit steps first (case 3));
  *   JAC2JAC (a, b, g, d), JAC2CHEB (a, b), CHEB2JAC (g, d), all > -1 (Sec.
  *   5.3): a change of the second parameter is done first by the reflection
- *   P_k^(a,b)(-x) = (-1)^k P_k^(b,a)(x), then the first; a parameter that
- *   drops by more than 1 goes down in unit steps first (case 4), every stage
- *   is then case 2 (case 1 banded for integer rises, case 3 with row 0
- *   computed directly when first + second <= -1);  LAG2LAG (a1, a2) with
- *   a1, a2 > -1.  LEG2CHEB / CHEB2LEG take none.
+ *   P_k^(a,b)(-x) = (-1)^k P_k^(b,a)(x), then the first; each change is a
+ *   banded stage for a whole-number rise (case 1), unit steps for a
+ *   whole-number drop, and otherwise unit steps down to a level in (-1, 0]
+ *   (in (0, 1] when both parameters are >= 1), the fractional case-2 stage
+ *   there (case 3 with row 0 computed directly when first + second <= -1),
+ *   and one banded rise back up (case 4; the order keeps the FFT stage where
+ *   D1 and D2 amplify its rounding least);
+ *   LAG2LAG (a1, a2) with a1, a2 > -1.  LEG2CHEB / CHEB2LEG take none.
  *   degree >= 0; 0 < tol < 1; flags: THX_FLAG_*.
  * On success *out owns device memory until thx_plan_destroy.  Errors:
  * THX_INVALID_ARGUMENT (out == NULL, degree < 0, tol outside (0,1), bad params),
  * THX_UNSUPPORTED (unknown kind), THX_OUT_OF_MEMORY,
- * THX_HIP_ERROR.  THX_TOL_NOT_REACHED returns a usable plan. */
+ * THX_HIP_ERROR.  THX_TOL_NOT_REACHED returns a usable plan (rank cap reached
+ * first, or tol below the double-precision floor). */
 thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, int nparams,
                            int64_t degree, double tol, thx_precision prec, uint32_t flags,
                            hipStream_t stream);
@@ -112,6 +126,23 @@ thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, 
  * degree out of range, ld too small, batch < 0 or above the limit), THX_HIP_ERROR. */
 thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
                        int64_t batch, int64_t ld, hipStream_t stream);
+
+/* Variable-length members on device offsets (the paper's batches of Sec. 2.1
+ * with one factorisation reused for every member): member i occupies
+ * alpha[off[i] .. off[i+1] - 1] and beta at the same places, so its degree is
+ * off[i+1] - off[i] - 1; d_offsets is a DEVICE array of count + 1 int64 and
+ * total is the length of the alpha and beta arrays.  Members whose degree
+ * exceeds the plan's, whose range leaves [0, total) or whose offsets decrease
+ * are skipped (their beta entries untouched) and, when d_skipped (a DEVICE
+ * int64, caller-initialised) is not NULL, counted there with an atomic add;
+ * empty members are skipped silently.  The degrees are derived on the device,
+ * so nothing synchronises; every member runs at the plan's FFT length (for many
+ * members of very different degrees, thx_batch groups them by length instead).
+ * count <= 65535 except on the dense path (3).  Errors: THX_INVALID_ARGUMENT
+ * (null plan, null pointers with count > 0, count or total negative, count
+ * above the limit), THX_OUT_OF_MEMORY, THX_HIP_ERROR. */
+thx_status thx_execute_varlen(const thx_plan *plan, const double *alpha, double *beta, const int64_t *d_offsets,
+                              int64_t count, int64_t total, int64_t *d_skipped, hipStream_t stream);
 
 /* Release a plan (synchronises nothing; the caller must ensure no execution of
  * it is still running).  NULL is accepted. */
@@ -185,8 +216,10 @@ int32_t thx_plan_partial_groups(const thx_plan *plan, int64_t batch);
  * THX_INVALID_ARGUMENT (null plan, batch < 1), THX_OUT_OF_MEMORY, THX_HIP_ERROR. */
 thx_status thx_plan_autotune(thx_plan *plan, int64_t batch, hipStream_t stream);
 
-/* Largest residual diagonal entry of part `part` at termination, relative to
- * max diag(H) (the achieved pivoted-Cholesky tolerance). */
+/* The tolerance the factorisation of Hankel part `part` achieved, in the units
+ * of thx_plan_create's tol (<= tol unless the plan returned THX_TOL_NOT_REACHED):
+ * the largest weighted residual diagonal at termination, converted by the same
+ * factor.  -1 for paths without a factorisation. */
 double thx_plan_achieved_tol(const thx_plan *plan, int part);
 
 /* Copy the normalised Cholesky columns of Hankel part `part` to host memory:
@@ -197,9 +230,16 @@ thx_status thx_plan_factors(const thx_plan *plan, int part, double *ell, int32_t
                             int64_t *n_out, hipStream_t stream);
 
 /* One-shot conversions with an internal plan cache keyed by (kind, params,
- * degree, tol, prec): the first call for a key creates the plan (synchronising
- * `stream` once), later calls only execute.  Same buffer conventions as
- * thx_execute with ld = N+1. */
+ * degree, tol, prec, device): the first call for a key creates the plan
+ * (synchronising `stream` once), later calls only execute.  Same buffer
+ * conventions as thx_execute with ld = N+1.  Calls with the same key share one
+ * workspace and are serialised: a call waits on the host while another thread's
+ * call with that key launches, its work waits on the device (an event) for the
+ * previous call's work on any stream, and a call with a larger batch than any
+ * before it first waits on the host for that work.  Calls with different keys
+ * run concurrently.  The paper's commands leg2cheb, cheb2leg, ultra2ultra,
+ * jac2jac(v,a,b,g,d), jac2cheb and cheb2jac (Sec. 1, 5.1-5.3) and Laguerre
+ * (Sec. 5.4). */
 thx_status thx_leg2cheb(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
                         thx_precision prec, hipStream_t stream);
 thx_status thx_cheb2leg(const double *alpha, double *beta, int64_t N, int64_t batch, double tol,
@@ -209,7 +249,17 @@ thx_status thx_ultra2ultra(const double *alpha, double *beta, int64_t N, int64_t
                            hipStream_t stream);
 thx_status thx_lag2lag(const double *alpha, double *beta, int64_t N, int64_t batch, double alpha1,
                        double alpha2, double tol, thx_precision prec, hipStream_t stream);
-/* Drop every cached plan (synchronises the device). */
+/* Jacobi P^(a,b) -> P^(g,d) (Sec. 5.3), parameters > -1 (THX_INVALID_ARGUMENT otherwise). */
+thx_status thx_jac2jac(const double *alpha, double *beta, int64_t N, int64_t batch, double a, double b, double g,
+                       double d, double tol, thx_precision prec, hipStream_t stream);
+/* Jacobi P^(a,b) -> Chebyshev T (Sec. 5.3, T_k = P_k^(-1/2,-1/2) / P_k^(-1/2,-1/2)(1)). */
+thx_status thx_jac2cheb(const double *alpha, double *beta, int64_t N, int64_t batch, double a, double b,
+                        double tol, thx_precision prec, hipStream_t stream);
+/* Chebyshev T -> Jacobi P^(g,d) (Sec. 5.3). */
+thx_status thx_cheb2jac(const double *alpha, double *beta, int64_t N, int64_t batch, double g, double d,
+                        double tol, thx_precision prec, hipStream_t stream);
+/* Drop every cached plan: waits for every cached plan's calls (host and device),
+ * then synchronises the device.  No one-shot call may start meanwhile. */
 thx_status thx_cache_clear(void);
 
 /* Mixed-degree batches (Fig. 1 applied to many polynomials; one pivoted
@@ -283,7 +333,8 @@ thx_status thx_plan_enable_timing(thx_plan *plan, uint32_t phases);
 thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);
 
 const char *thx_status_string(thx_status s);
-int thx_last_hip_error(void);
+/* hipError_t of the last failed HIP call made by this thread inside the library */
+hipError_t thx_last_hip_error(void);
 
 #ifdef __cplusplus
 }

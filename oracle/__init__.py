@@ -65,6 +65,8 @@ def _load():
         lib.orc_matvec.argtypes = [ctypes.c_int, dp, i64, dp, dp,
                                    ctypes.POINTER(ctypes.c_int64), i64, ctypes.c_int]
         lib.orc_matvec.restype = ctypes.c_int
+        lib.orc_matvec_abs.argtypes = lib.orc_matvec.argtypes
+        lib.orc_matvec_abs.restype = ctypes.c_int
         lib.orc_dense.argtypes = [ctypes.c_int, dp, i64, dp]
         lib.orc_dense.restype = ctypes.c_int
         lib.orc_absmax.argtypes = [ctypes.c_int, dp, i64]
@@ -90,11 +92,13 @@ def _params(kind: str, params) -> np.ndarray:
     return p
 
 
-def matvec(kind: str, alpha, params=(), rows=None, nthreads: int = 0) -> np.ndarray:
+def matvec(kind: str, alpha, params=(), rows=None, nthreads: int = 0, absolute: bool = False) -> np.ndarray:
     """beta = A alpha (all rows, or only ``rows``) for one coefficient vector.
 
     kind: 'leg2cheb', 'cheb2leg', 'ultra2ultra' (params l1, l2), 'jac2jac_b'
     (params a, b, g: Jacobi (a,b) -> (g,b)), 'lag2lag' (params a1, a2).
+    absolute: return |A| |alpha| instead (the rounding scale of each row, for
+    error bars).
     """
     lib = _load()
     a = np.ascontiguousarray(alpha, dtype=np.float64)
@@ -107,7 +111,8 @@ def matvec(kind: str, alpha, params=(), rows=None, nthreads: int = 0) -> np.ndar
         r = np.ascontiguousarray(rows, dtype=np.int64)
         out = np.empty(r.shape[0], dtype=np.float64)
         rp, nr = r.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), r.shape[0]
-    rc = lib.orc_matvec(KINDS[kind], _dptr(p), N, _dptr(a), _dptr(out), rp, nr, int(nthreads))
+    fn = lib.orc_matvec_abs if absolute else lib.orc_matvec
+    rc = fn(KINDS[kind], _dptr(p), N, _dptr(a), _dptr(out), rp, nr, int(nthreads))
     if rc != 0:
         raise ValueError(f"oracle matvec failed (rc={rc}) for {kind} {params} N={N}")
     return out

@@ -121,6 +121,7 @@ typedef struct {
     int8_t *jb_zeroE;
     ldbl *jb_D;     /* row prefactor, j = 0..N                                      */
     double p[4];
+    int absmode;    /* row sums of |A_jk| |alpha_k| instead of A_jk alpha_k (bar scales) */
 } orc_ctx;
 
 static inline void neumaier_add(ldbl *s, ldbl *c, ldbl t)
@@ -179,7 +180,8 @@ static double row(const orc_ctx *C, int64_t j, const double *alpha)
     int64_t step = (C->kind == ORC_JAC2JAC || C->kind == ORC_LAG2LAG) ? 1 : 2;
     for (int64_t k = j; k <= C->N; k += step) {
         if (alpha[k] == 0.0) continue;
-        neumaier_add(&s, &c, entry(C, j, k) * (ldbl)alpha[k]);
+        if (C->absmode) neumaier_add(&s, &c, fabsl(entry(C, j, k)) * fabsl((ldbl)alpha[k]));
+        else neumaier_add(&s, &c, entry(C, j, k) * (ldbl)alpha[k]);
     }
     return (double)(s + c);
 }
@@ -331,7 +333,8 @@ static double row_jacobi(const orc_ctx *C, int64_t j, const double *alpha)
         int z;
         ldbl a = jacobi_entry(C, j, k, lgD, &z);
         if (z) continue;
-        neumaier_add(&s, &cc, a * (ldbl)alpha[k]);
+        if (C->absmode) neumaier_add(&s, &cc, fabsl(a) * fabsl((ldbl)alpha[k]));
+        else neumaier_add(&s, &cc, a * (ldbl)alpha[k]);
     }
     return (double)(s + cc);
 }
@@ -343,13 +346,14 @@ static double row_jacobi(const orc_ctx *C, int64_t j, const double *alpha)
 /* beta = A alpha for rows `rows[0..nrows)` (all rows 0..N when rows == NULL).
  * alpha: N+1 doubles.  beta: N+1 doubles when rows == NULL, else nrows doubles.
  * nthreads <= 0 uses the OpenMP default.  Returns 0 on success. */
-int orc_matvec(int kind, const double *params, int64_t N, const double *alpha, double *beta,
-               const int64_t *rows, int64_t nrows, int nthreads)
+static int matvec_mode(int kind, const double *params, int64_t N, const double *alpha, double *beta,
+                       const int64_t *rows, int64_t nrows, int nthreads, int absmode)
 {
     if (N < 0 || !alpha || !beta) return -1;
     orc_ctx C;
     int rc = ctx_init(&C, kind, params, N);
     if (rc) return rc;
+    C.absmode = absmode;
     int64_t R = rows ? nrows : N + 1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -367,23 +371,44 @@ int orc_matvec(int kind, const double *params, int64_t N, const double *alpha, d
     return bad ? -1 : 0;
 }
 
-/* Dense matrix A (row-major, (N+1)^2 doubles) for small N. */
+int orc_matvec(int kind, const double *params, int64_t N, const double *alpha, double *beta,
+               const int64_t *rows, int64_t nrows, int nthreads)
+{
+    return matvec_mode(kind, params, N, alpha, beta, rows, nrows, nthreads, 0);
+}
+
+/* (|A| |alpha|)_j = sum_k |A_jk| |alpha_k| for the same rows: the scale of the
+ * rounding error of any evaluation of row j (test bars only). */
+int orc_matvec_abs(int kind, const double *params, int64_t N, const double *alpha, double *beta,
+                   const int64_t *rows, int64_t nrows, int nthreads)
+{
+    return matvec_mode(kind, params, N, alpha, beta, rows, nrows, nthreads, 1);
+}
+
+/* Dense matrix A (row-major, (N+1)^2 doubles), entry by entry. */
 int orc_dense(int kind, const double *params, int64_t N, double *A)
 {
     if (N < 0 || !A) return -1;
     orc_ctx C;
     int rc = ctx_init(&C, kind, params, N);
     if (rc) return rc;
-    double *e = (double *)calloc((size_t)(N + 1), sizeof(double));
-    if (!e) { ctx_free(&C); return -2; }
-    for (int64_t k = 0; k <= N; ++k) {
-        e[k] = 1.0;
-        for (int64_t j = 0; j <= N; ++j)
-            A[j * (N + 1) + k] = (j > k) ? 0.0
-                                 : (kind == ORC_JAC2JAC ? row_jacobi(&C, j, e) : row(&C, j, e));
-        e[k] = 0.0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j <= N; ++j) {
+        const f128 lgD = kind == ORC_JAC2JAC ? jacobi_lgD(&C, j) : 0;
+        for (int64_t k = 0; k <= N; ++k) {
+            double v = 0.0;
+            if (k >= j) {
+                if (kind == ORC_JAC2JAC) {
+                    int z;
+                    ldbl e = jacobi_entry(&C, j, k, lgD, &z);
+                    v = z ? 0.0 : (double)e;
+                } else {
+                    v = (double)entry(&C, j, k);
+                }
+            }
+            A[j * (N + 1) + k] = v;
+        }
     }
-    free(e);
     ctx_free(&C);
     return 0;
 }

@@ -60,6 +60,10 @@ _sig("thx_leg2cheb", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, ctypes.c_int, _vp
 _sig("thx_cheb2leg", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, ctypes.c_int, _vp)
 _sig("thx_ultra2ultra", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
 _sig("thx_lag2lag", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
+_sig("thx_jac2jac", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
+_sig("thx_jac2cheb", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
+_sig("thx_cheb2jac", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
+_sig("thx_execute_varlen", ctypes.c_int, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp)
 _sig("thx_cache_clear", ctypes.c_int)
 _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
@@ -74,7 +78,7 @@ _sig("thx_batch_buckets", _i32, _vp)
 _sig("thx_batch_bucket_info", ctypes.c_int, _vp, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
      ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32))
 _sig("thx_status_string", ctypes.c_char_p, ctypes.c_int)
-_sig("thx_last_hip_error", ctypes.c_int)
+_sig("thx_last_hip_error", ctypes.c_int)   # hipError_t (an enum of int size)
 
 
 class ThxError(RuntimeError):
@@ -223,6 +227,23 @@ class Plan:
                "thx_execute")
         return beta
 
+    def execute_varlen(self, alpha, beta, offsets, skipped=None, stream=None):
+        """thx_execute_varlen: members alpha[offsets[i]:offsets[i+1]] (offsets: int64 device tensor
+        of count + 1 entries; skipped: optional int64 device tensor of one entry, added to)."""
+        import torch
+        _check_tensor(alpha, "alpha")
+        _check_tensor(beta, "beta")
+        if not (offsets.is_cuda and offsets.dtype == torch.int64 and offsets.is_contiguous()):
+            raise TypeError("offsets must be a contiguous int64 tensor on the GPU")
+        if not alpha.is_contiguous() or not beta.is_contiguous() or alpha.numel() != beta.numel():
+            raise ValueError("contiguous alpha/beta of equal size required")
+        if skipped is not None and not (skipped.is_cuda and skipped.dtype == torch.int64):
+            raise TypeError("skipped must be an int64 tensor on the GPU")
+        _check(_lib.thx_execute_varlen(self._h, _ptr(alpha), _ptr(beta), _ptr(offsets), offsets.numel() - 1,
+                                       alpha.numel(), _ptr(skipped) if skipped is not None else None,
+                                       _stream(stream)), "thx_execute_varlen")
+        return beta
+
 
 class Batch:
     """Owns a thx_batch* (thx_batch_create / thx_batch_destroy): mixed degrees, CSR layout."""
@@ -290,7 +311,7 @@ def thx_leg2cheb(alpha, beta, tol=1e-15, prec=FP64, stream=None):
     return _oneshot("thx_leg2cheb", alpha, beta, tol, prec, stream=stream)
 
 
-def thx_cheb2leg(alpha, beta, tol=1e-17, prec=FP64, stream=None):
+def thx_cheb2leg(alpha, beta, tol=1e-15, prec=FP64, stream=None):
     return _oneshot("thx_cheb2leg", alpha, beta, tol, prec, stream=stream)
 
 
@@ -300,6 +321,18 @@ def thx_ultra2ultra(alpha, beta, lambda1, lambda2, tol=1e-15, prec=FP64, stream=
 
 def thx_lag2lag(alpha, beta, alpha1, alpha2, tol=1e-15, prec=FP64, stream=None):
     return _oneshot("thx_lag2lag", alpha, beta, alpha1, alpha2, tol, prec, stream=stream)
+
+
+def thx_jac2jac(alpha, beta, a, b, g, d, tol=1e-15, prec=FP64, stream=None):
+    return _oneshot("thx_jac2jac", alpha, beta, a, b, g, d, tol, prec, stream=stream)
+
+
+def thx_jac2cheb(alpha, beta, a, b, tol=1e-15, prec=FP64, stream=None):
+    return _oneshot("thx_jac2cheb", alpha, beta, a, b, tol, prec, stream=stream)
+
+
+def thx_cheb2jac(alpha, beta, g, d, tol=1e-15, prec=FP64, stream=None):
+    return _oneshot("thx_cheb2jac", alpha, beta, g, d, tol, prec, stream=stream)
 
 
 def thx_cache_clear():

@@ -211,8 +211,10 @@ __global__ __launch_bounds__(PC_NT) void k_pchol_init(PcholArgs a)
     for (int q = 0; q < a.parts; ++q) {
         double v = 0.0;
         if (i < a.nc) {
-            if (i >= a.a0[q] && i < a.n[q]) v = a.hk[2 * i + hk_offset(a, q)];
-            a.d[q * a.nc + i] = v;
+            double dv = 0.0;
+            if (i >= a.a0[q] && i < a.n[q]) dv = a.hk[2 * i + hk_offset(a, q)];
+            a.d[q * a.nc + i] = dv;
+            v = a.w[q * a.nc + i] * dv;
         }
         int idx = (int)i;
         block_argmax(v, idx, sv, si);
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_pchol_select(PcholArgs a, int r)
         if (threadIdx.x == 0) {
             if (r == 0) st->dmax0[q] = v;
             const double d0 = st->dmax0[q];
-            if (r >= a.kcap || !(v > a.tol * d0) || !(v > 0.0)) {
+            if (r >= a.kcap || !(v > st->eps[q] * d0) || !(v > 0.0)) {
                 st->done[q] = 1;
                 st->K[q] = r;
                 st->dfinal[q] = d0 > 0.0 ? fmax(v, 0.0) / d0 : 0.0;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_pchol_select(PcholArgs a, int r)
             } else {
                 st->active[q] = 1;
                 st->cur_p[q] = idx;
-                st->cur_piv[q] = v;
+                st->cur_piv[q] = a.d[q * a.nc + idx]; // unweighted: the Schur step divides by it
                 st->piv[q][r] = idx;
                 st->pval[q][r] = v;
                 go = 1;
@@ -318,6 +320,7 @@ __global__ __launch_bounds__(PC_NT) void k_pchol_column(PcholArgs a, int r)
                 if (!(dn > 0.0) || i == st->cur_p[q]) dn = 0.0;
                 a.d[q * a.nc + i] = dn;
             }
+            dn *= a.w[q * a.nc + i];
         }
         int idx = (int)i;
         block_argmax(dn, idx, sv, si);
@@ -462,6 +465,118 @@ void launch_pack(const KindDesc &k, const int64_t *off, const int64_t *deg, cons
 }
 template void launch_pack<double>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
 template void launch_pack<float>(const KindDesc &, const int64_t *, const int64_t *, const double *, int64_t, int64_t, int64_t, void *, int64_t, hipStream_t);
+
+// ============================================================================
+// a2 (continued): pivot weights and stopping threshold of the pivoted Cholesky
+// ============================================================================
+// The truncation error of A = D1 (T o H) D2 is D1 (T o E) D2 alpha with E the
+// PSD residual of H, |E_jk| <= sqrt(E_jj E_kk).  Writing w_j = |D1_j D2_j| and
+// r_j = sqrt|D1_j / D2_j|, |D1_j| sqrt(E_jj) = r_j sqrt(w_j E_jj) and
+// |D2_k| sqrt(E_kk) = sqrt(w_k E_kk) / r_k, so
+//   |beta error_j| <= Tmax amp max_i(w_i E_ii) ||alpha||_1,  amp = max_{j<=k} r_j / r_k.
+// Pivoting on w_i d_i is the diagonal pivoting of S H S, S = diag(sqrt w): it
+// removes first the residual that D1 and D2 amplify most.  Stopping once
+// max w_i d_i <= eps max w_i H_ii with eps = 2 tol |t_0| / (amp Tmax) bounds the
+// error by 2 tol max_j |A_jj| ||alpha||_1 (max w_i H_ii |t_0| = max |A_jj|).
+
+// lane i of part q holds coefficient j = 2i + q (parity-split kinds) or j = i
+__device__ __forceinline__ int64_t part_index(const KindDesc &k, int q, int64_t i)
+{
+    return k.parity ? 2 * i + q : i;
+}
+
+__global__ void k_pchol_w(KindDesc k, PcholArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.nc) return;
+    for (int q = 0; q < a.parts; ++q) {
+        double w = 0.0;
+        if (i >= a.a0[q] && i < a.n[q]) {
+            const int64_t j = part_index(k, q, i);
+            w = fabs(d1_of(k, j) * d2_of(k, j));
+            if (!(w < INFINITY)) w = 0.0; // also NaN
+        }
+        a.w[q * a.nc + i] = w;
+    }
+}
+
+constexpr int AMP_NT = 1024;
+
+__device__ __forceinline__ double amp_r(const KindDesc &k, const PcholArgs &a, int q, int64_t i)
+{
+    if (!(a.w[q * a.nc + i] > 0.0)) return 0.0; // outside the part, or a zero factor
+    const int64_t j = part_index(k, q, i);
+    return sqrt(fabs(d1_of(k, j) / d2_of(k, j)));
+}
+
+__device__ double block_max(double v, double *sv)
+{
+    const int t = threadIdx.x;
+    sv[t] = v;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (t < h) sv[t] = fmax(sv[t], sv[t + h]);
+        __syncthreads();
+    }
+    const double m = sv[0];
+    __syncthreads();
+    return m;
+}
+
+__global__ __launch_bounds__(AMP_NT) void k_pchol_amp(KindDesc k, PcholArgs a, const double *tsym, int64_t nt,
+                                                      double tol, double floor_rel)
+{
+    __shared__ double sv[AMP_NT];
+    __shared__ double pre[AMP_NT];
+    const int t = threadIdx.x;
+    // Tmax and |t_0| of the Toeplitz symbol
+    double tm = 0.0;
+    for (int64_t m = t; m < nt; m += AMP_NT) tm = fmax(tm, fabs(tsym[m]));
+    const double Tmax = block_max(tm, sv);
+    const double t0 = fabs(tsym[0]) > 0.0 ? fabs(tsym[0]) : Tmax;
+    for (int q = 0; q < a.parts; ++q) {
+        // amp = max over i <= i' of r_i / r_i' (indices with w > 0): chunked, with an
+        // exclusive prefix maximum of the chunk maxima
+        const int64_t lo = a.a0[q], hi = a.n[q];
+        const int64_t len = hi > lo ? hi - lo : 0;
+        const int64_t C = (len + AMP_NT - 1) / AMP_NT;
+        const int64_t c0 = lo + (int64_t)t * C, c1 = c0 + C < hi ? c0 + C : hi;
+        double cm = 0.0;
+        for (int64_t i = c0; i < c1; ++i) cm = fmax(cm, amp_r(k, a, q, i));
+        pre[t] = cm;
+        __syncthreads();
+        if (t == 0) {
+            double run = 0.0;
+            for (int u = 0; u < AMP_NT; ++u) {
+                const double x = pre[u];
+                pre[u] = run;
+                run = fmax(run, x);
+            }
+        }
+        __syncthreads();
+        double run = pre[t], best = 0.0;
+        for (int64_t i = c0; i < c1; ++i) {
+            const double r = amp_r(k, a, q, i);
+            if (!(r > 0.0)) continue;
+            run = fmax(run, r);
+            best = fmax(best, run / r);
+        }
+        const double amp = fmax(block_max(best, sv), 1e-300);
+        if (t == 0) {
+            const double e = Tmax > 0.0 ? 2.0 * tol * t0 / (amp * Tmax) : tol;
+            a.st->eps[q] = fmax(e, floor_rel);
+            a.st->escale[q] = Tmax > 0.0 ? amp * Tmax / (2.0 * t0) : 1.0;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_pchol_weights(const KindDesc &k, const PcholArgs &a, const double *tsym, int64_t nt, double tol,
+                          double floor_rel, hipStream_t s)
+{
+    k_pchol_w<<<(unsigned)((a.nc + 255) / 256), 256, 0, s>>>(k, a);
+    k_pchol_amp<<<1, AMP_NT, 0, s>>>(k, a, tsym, nt, tol, floor_rel);
+}
 
 // ============================================================================
 // a6: sum the partial results, remove the circulant alias, beta = D1 w
@@ -612,7 +727,7 @@ __global__ __launch_bounds__(256) void k_row0_part(KindDesc k, VecRef vr, const 
     int64_t base, N;
     vec_of(vr, b, ld, N0, base, N);
     const double *al = alpha + base;
-    const int64_t cmax = k.parity ? N / 2 : N; // last term index
+    const int64_t cmax = N < 0 ? -1 : (k.parity ? N / 2 : N); // last term index (none: empty vector)
     const int64_t c0 = (int64_t)blockIdx.x * chunk, c1 = min(cmax + 1, c0 + chunk);
     double acc = 0.0;
     if (k.parity) {
@@ -654,6 +769,31 @@ void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *de
     k_row0_part<<<dim3((unsigned)P, (unsigned)batch), 256, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tsym, hk,
                                                                   chunk, part);
     k_row0_sum<<<(unsigned)batch, ROW0_PMAX, 0, s>>>(k, part, (int)P, row0);
+}
+
+// Per-member degrees of a variable-length execution from device offsets:
+// member i is alpha[off[i] .. off[i+1]-1].  Members that are malformed, reach
+// beyond `total` or exceed the plan's degree are skipped (degree -1, nothing
+// read or written) and counted in *skipped when it is given; empty members are
+// skipped silently.
+__global__ void k_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nmax, int64_t *off2,
+                         int64_t *deg, unsigned long long *skipped)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t o0 = off[i], o1 = off[i + 1], n = o1 - o0 - 1;
+    const bool ok = o0 >= 0 && o1 <= total && n >= 0 && n <= nmax;
+    off2[i] = ok ? o0 : 0;
+    deg[i] = ok ? n : -1;
+    if (!ok && n != -1 && skipped) atomicAdd(skipped, 1ull);
+}
+
+void launch_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nmax, int64_t *off2, int64_t *deg,
+                   int64_t *skipped, hipStream_t s)
+{
+    const int nt = 256;
+    k_varlen<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(off, count, total, nmax, off2, deg,
+                                                               (unsigned long long *)skipped);
 }
 
 // ============================================================================

@@ -31,17 +31,22 @@ struct KindDesc {
 };
 
 // Device state of the pivoted Cholesky (two independent parts at most).
+// Pivots are chosen and the factorisation stopped on the weighted residual
+// diagonal w_i d_i, w_i = |D1_j D2_j| (the diagonal of S H S with
+// S = diag(sqrt|D1 D2|)); see k_pchol_amp for the threshold.
 constexpr int KMAX = 128;
 struct PcholState {
     int K[2];
     int done[2];
     int active[2];
     int cur_p[2];
-    double cur_piv[2];
-    double dmax0[2];
-    double dfinal[2];
+    double cur_piv[2];    // unweighted residual diagonal at the current pivot
+    double dmax0[2];      // largest weighted diagonal w_i H_ii
+    double dfinal[2];     // largest weighted residual at termination / dmax0
+    double eps[2];        // stopping threshold relative to dmax0
+    double escale[2];     // amp Tmax / (2 |t_0|): dfinal in units of the API tolerance
     int piv[2][KMAX];
-    double pval[2][KMAX]; // pivot values (residual diagonal at p_r when chosen)
+    double pval[2][KMAX]; // weighted pivot values (w_p d_p when chosen)
     double R[2][KMAX][KMAX]; // R[q][r][i] = normalised column i of part q at pivot p_r
 };
 
@@ -63,6 +68,7 @@ void launch_jacobi_diag(double *out, int64_t count, int which, double a, double 
 // part (rows below are excluded).  ell: [KMAX slots][nc] complex doubles.
 struct PcholArgs {
     const double *hk;
+    double *w;        // pivot weights |D1_j D2_j| [parts][nc] (zero outside a part)
     double *d;        // residual diagonals [parts][nc]
     double *ell;      // (double*) of the complex [slot][nc] array
     int64_t nc;
@@ -76,6 +82,12 @@ struct PcholArgs {
     int *pi;          // block partial argmax [parts][nblk]
     int nblk;
 };
+// Weights w and, per part, the threshold eps = max(floor, 2 tol |t_0| / (amp Tmax))
+// with amp = max_{j <= k} r_j / r_k, r = sqrt|D1 / D2| and Tmax = max |t_m| over
+// the first nt symbol entries; then |beta error| <= 2 tol max_j |A_jj| ||alpha||_1
+// for the truncation.  Writes st->eps and st->escale.
+void launch_pchol_weights(const KindDesc &k, const PcholArgs &a, const double *tsym, int64_t nt, double tol,
+                          double floor_rel, hipStream_t s);
 void launch_pchol_init(const PcholArgs &a, hipStream_t s);
 void launch_pchol_step(const PcholArgs &a, int r, hipStream_t s);
 
@@ -118,6 +130,11 @@ constexpr int ROW0_PMAX = 256;
 void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                         int64_t ld, int64_t N, int64_t batch, const double *tsym, const double *hk,
                         double *part, double *row0, hipStream_t s);
+
+// variable-length members from device offsets (count + 1 entries): sanitised
+// offsets and degrees (-1: skipped; *skipped counts the non-empty ones, may be null)
+void launch_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nmax, int64_t *off2, int64_t *deg,
+                   int64_t *skipped, hipStream_t s);
 
 // ---- direct O(N^2) ----------------------------------------------------------------
 void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,

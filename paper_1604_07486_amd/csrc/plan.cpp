@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <tuple>
@@ -155,7 +156,9 @@ struct thx_plan {
     int64_t L = 0;
     MultiPassGeom geom{};
     int K[2] = {-1, -1};
-    double dfinal[2] = {0, 0};
+    double dfinal[2] = {0, 0}; // largest weighted residual at termination / largest weighted diagonal
+    double eps[2] = {0, 0};    // stopping threshold in the same units
+    double escale[2] = {1, 1}; // converts those units to the API tolerance (thx_plan_achieved_tol)
     int S = 0;            // complex FFT slots
     int slots_alloc = 0;  // allocated slots in ell64
     bool tol_reached = true;
@@ -172,7 +175,7 @@ struct thx_plan {
     void *twL1 = nullptr, *twL2 = nullptr, *twA = nullptr; // three-pass tables
     double *tw64_keep[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *pivots[2] = {nullptr, nullptr}; // host copies
-    std::vector<double> prel[2];             // pivot value / largest diagonal, per rank
+    std::vector<double> prel[2];             // weighted pivot value / largest weighted diagonal, per rank
     int S_full = 0; // slots of the whole factorisation (S: those run in this plan's precision)
     // THX_FP64_TAIL32: the trailing slots, whose pivots are so small that single
     // precision rounds them below the Hankel tolerance, run as a single-precision
@@ -189,6 +192,8 @@ struct thx_plan {
     double *sfx_tot = nullptr;   // path 4: [batch][chunks][2] chunk totals
     int64_t U_slots = 0;
     int Gmax = 0;
+    int64_t *vl_off = nullptr, *vl_deg = nullptr; // variable-length executions: per-member offsets, degrees
+    int64_t vl_count = 0;
     // per-phase event timing
     uint32_t timing = 0; // bit i: phase i is timed
     std::vector<hipEvent_t> ev_pool;
@@ -227,6 +232,8 @@ struct thx_plan {
         dfree(row0);
         dfree(row0_part);
         dfree(sfx_tot);
+        dfree(vl_off);
+        dfree(vl_deg);
         delete[] pivots[0];
         delete[] pivots[1];
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -403,6 +410,11 @@ void build_tables(thx_plan *p, hipStream_t s)
     launch_check();
 }
 
+// Lowest stopping threshold of the pivoted Cholesky, relative to the largest
+// weighted diagonal: below a few rounding units of double precision the
+// residual diagonal is noise and further pivots would only chase it.
+constexpr double PCHOL_FLOOR = 4.440892098500626e-16; // 2^-51
+
 void run_pchol(thx_plan *p, hipStream_t s)
 {
     const int64_t maxn = std::max(p->npart[0] - p->a0[0], p->parts == 2 ? p->npart[1] - p->a0[1] : 0);
@@ -411,6 +423,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
     p->ell64 = dalloc<double>(2 * (int64_t)p->slots_alloc * p->ncs);
     hip_check(hipMemsetAsync(p->ell64, 0, sizeof(double) * 2 * (size_t)p->slots_alloc * p->ncs, s));
     double *d = dalloc<double>((int64_t)p->parts * p->ncs);
+    double *w = dalloc<double>((int64_t)p->parts * p->ncs);
     PcholState *st = dalloc<PcholState>(1);
     hip_check(hipMemsetAsync(st, 0, sizeof(PcholState), s));
     const int nblk = (int)((p->ncs + 255) / 256);
@@ -418,6 +431,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
     int *pi = dalloc<int>((int64_t)p->parts * nblk);
     PcholArgs a{};
     a.hk = p->hk;
+    a.w = w;
     a.d = d;
     a.ell = p->ell64;
     a.nc = p->ncs;
@@ -432,6 +446,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
     a.pv = pv;
     a.pi = pi;
     a.nblk = nblk;
+    launch_pchol_weights(p->kd, a, p->tsym, p->nc, p->tol, PCHOL_FLOOR, s);
     launch_pchol_init(a, s);
     launch_check();
     PcholState hs;
@@ -452,7 +467,12 @@ void run_pchol(thx_plan *p, hipStream_t s)
     for (int q = 0; q < p->parts; ++q) {
         p->K[q] = hs.K[q];
         p->dfinal[q] = hs.dfinal[q];
-        if (hs.K[q] >= kcap && hs.dfinal[q] > p->tol) p->tol_reached = false;
+        p->eps[q] = hs.eps[q];
+        p->escale[q] = hs.escale[q];
+        // not reached: the rank cap came first, or tol lies below the floor
+        // (the threshold was raised to it)
+        if ((hs.K[q] >= kcap && hs.dfinal[q] > hs.eps[q]) || hs.eps[q] * hs.escale[q] > p->tol * (1 + 1e-12))
+            p->tol_reached = false;
         p->pivots[q] = new int32_t[std::max(1, hs.K[q])];
         for (int r = 0; r < hs.K[q]; ++r) p->pivots[q][r] = hs.piv[q][r];
         p->prel[q].resize(std::max(0, hs.K[q]));
@@ -461,6 +481,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
     p->S = p->parts == 2 ? std::max(p->K[0], p->K[1]) : (p->K[0] + 1) / 2;
     p->S_full = p->S;
     dfree(d);
+    dfree(w);
     dfree(st);
     dfree(pv);
     dfree(pi);
@@ -468,7 +489,7 @@ void run_pchol(thx_plan *p, hipStream_t s)
 
 // ---- FP64 plans with a single-precision tail (THX_FP64_TAIL32) ----
 // Slot r's term D_l~r T D_l~r x is of size piv_r / max diag(H) relative to the
-// largest.  Run in single precision, a whole plan whose first pivot is the
+// largest (weighted pivots: relative to the largest diagonal entry of A).  Run in single precision, a whole plan whose first pivot is the
 // largest diagonal errs by at most 2.7e-8 of ||alpha||_1 (leg2cheb at 2^16 and
 // 2^20 with every rank in single precision, measured), so slots whose every
 // pivot is at most tol * 2^23 of the largest diagonal add at most ~tol/4
@@ -485,8 +506,8 @@ int tail_first_slot(const thx_plan *p)
     double gain = TAIL32_PIVOT_GAIN;
     // THX_TAIL32_LOG2GAIN: log2 of the gain (measurements of the error it trades)
     if (const char *e = getenv("THX_TAIL32_LOG2GAIN")) gain = std::ldexp(1.0, atoi(e));
-    const double lim = p->tol * gain;
-    auto small = [&](int q, int r) { return r >= p->K[q] || p->prel[q][r] <= lim; };
+    // pivots within `gain` of the stopping threshold
+    auto small = [&](int q, int r) { return r >= p->K[q] || p->prel[q][r] <= p->eps[q] * gain; };
     auto slot_small = [&](int sl) {
         return p->parts == 2 ? small(0, sl) && small(1, sl) : small(0, 2 * sl) && small(0, 2 * sl + 1);
     };
@@ -661,6 +682,15 @@ thx_status create_chain(thx_plan **out, size_t n, Make &&make)
 // Jacobi conversions (Sec. 5.3): a change of the second parameter b -> d first
 // (reflected stage), then of the first a -> g; each stage must be case 2
 // (|a - g| < 1 or a - g = 1, and a + b > -1 so that the Hankel part is PSD).
+// Level at or below which a fractional Jacobi change between parameters with
+// the smaller one `lo` runs (see create_jacobi); THX_JAC_FRAC_LEVEL overrides it
+// (measurements of the routes).
+double jac_frac_level(double lo)
+{
+    if (const char *e = getenv("THX_JAC_FRAC_LEVEL")) return (double)atoi(e);
+    return lo < 1.0 ? 0.0 : 1.0;
+}
+
 thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_t degree, double tol,
                          thx_precision prec, uint32_t flags, hipStream_t s)
 {
@@ -675,23 +705,42 @@ thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_
         a = -0.5, b = -0.5, g = pv[0], d = pv[1];
         cheb_first = 2;
     }
-    // Sec. 5.3, case 4: while the first parameter must move by more than 1 (and
-    // not by a whole number upwards, which is one banded case-1 stage), move it
-    // by exactly 1 towards the target: down, T and H are constant (unit step,
-    // suffix sums); up, T is bidiagonal (banded).  The last stage moves it by at
-    // most 1 (case 2 or 3).  (A single case-2 stage over a larger rise is PSD
-    // but its diagonal scalings amplify rounding: measured 4e-9 for a rise of 3.)
+    // Sec. 5.3, cases 1 and 4.  A whole-number rise is one banded stage (case 1);
+    // a whole-number drop is that many unit steps (T and H constant: suffix sums).
+    // A fractional change x -> y runs its case-2 (or case-3) stage at low levels
+    // xl = x - kx, yl = y - ky in (lvl - 1, lvl] (so |xl - yl| < 1): kx unit steps
+    // down first, the fractional stage, then one banded rise by ky.  Sec. 5.3
+    // steps by whole numbers first and takes the fractional stage last; every
+    // order gives the same expansion, but the FFT's rounding is relative to the
+    // largest term of the whole vector and D1_j ~ j^(g+1) multiplies it, so the
+    // fractional stage loses accuracy as its parameters grow, while each unit
+    // step down grows the intermediate coefficients.  Measured on the GPU (double
+    // precision, degree 3000, error over max_j (|A||alpha|)_j): lvl = 0 is best
+    // while min(x, y) < 1 ((0.975 -> 0.847): 1e-15 against 1.4e-12 in place),
+    // lvl = 1 above ((1.7 -> 1.2): 3e-14 against 2.6e-12 at lvl 0 and 3.6e-11 at
+    // lvl 2; (2.7 -> 2.2): 1.4e-12 against 2.7e-9 at lvl 0).
     std::vector<JacStage> st;
     auto steps = [&](double x, double y, double other, int reflect) {
-        while (std::fabs(x - y) > 1.0 && !(y > x && neg_integer(x - y))) {
-            const double nx = x > y ? x - 1.0 : x + 1.0;
-            st.push_back(JacStage{x, other, nx, reflect, 0});
-            x = nx;
+        if (x == y) return;
+        const double dxy = y - x;
+        if (dxy == std::floor(dxy)) {
+            if (dxy > 0) {
+                st.push_back(JacStage{x, other, y, reflect, 0});
+            } else {
+                for (; x > y; x -= 1.0) st.push_back(JacStage{x, other, x - 1.0, reflect, 0});
+            }
+            return;
         }
-        st.push_back(JacStage{x, other, y, reflect, 0});
+        const double lvl = jac_frac_level(std::min(x, y));
+        const double kx = std::max(0.0, std::ceil(x - lvl)), ky = std::max(0.0, std::ceil(y - lvl));
+        const double xl = x - kx, yl = y - ky;
+        for (; x > xl + 0.5; x -= 1.0) st.push_back(JacStage{x, other, x - 1.0, reflect, 0});
+        st.push_back(JacStage{xl, other, yl, reflect, 0});
+        if (ky > 0) st.push_back(JacStage{yl, other, y, reflect, 0});
     };
     if (b != d) steps(b, d, a, 1); // (b, a) -> (d, a), reflected
-    if (a != g || st.empty()) steps(a, g, d, 0);
+    steps(a, g, d, 0);
+    if (st.empty()) st.push_back(JacStage{a, d, g, 0, 0}); // identity (Chebyshev ends still apply)
     st.front().cheb = cheb_first ? cheb_first : st.front().cheb;
     if (cheb_last) {
         if (cheb_first == 0 && st.size() == 1 && st[0].cheb == 0) st[0].cheb = 1;
@@ -1131,6 +1180,38 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     return THX_OK;
 }
 
+// Variable-length execution: members at device offsets, degrees derived on the
+// device (no host synchronisation), then the same launches as a batch bucket.
+thx_status do_execute_varlen(const thx_plan *cp, const double *alpha, double *beta, const int64_t *d_off,
+                             int64_t count, int64_t total, int64_t *d_skipped, hipStream_t s)
+{
+    thx_plan *p = const_cast<thx_plan *>(cp);
+    if (!p || count < 0 || total < 0 || (count > 0 && !d_off)) return THX_INVALID_ARGUMENT;
+    if (count == 0) return THX_OK;
+    if (!alpha || !beta) return THX_INVALID_ARGUMENT;
+    if (count > 65535 && !p->dense) return THX_INVALID_ARGUMENT; // grid.y limit of the launches
+    try {
+        if (count > p->vl_count) {
+            dfree(p->vl_off);
+            dfree(p->vl_deg);
+            p->vl_off = p->vl_deg = nullptr;
+            p->vl_count = 0;
+            p->vl_off = dalloc<int64_t>(count);
+            p->vl_deg = dalloc<int64_t>(count);
+            p->vl_count = count;
+        }
+        launch_varlen(d_off, count, total, p->N, p->vl_off, p->vl_deg, d_skipped, s);
+        launch_check();
+        execute_core(p, p->vl_off, p->vl_deg, alpha, beta, p->N, count, 0, s, std::max<int64_t>(total, 1));
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        return THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        return THX_OUT_OF_MEMORY;
+    }
+    return THX_OK;
+}
+
 // ---- autotuning: launch shapes, row length, dense vs FFT ------------------------
 // Candidates are timed with HIP events on zero-filled inputs of the expected
 // batch (values do not change the work), median of three after one warm-up.
@@ -1328,9 +1409,36 @@ thx_status autotune(thx_plan *p, int64_t batch, hipStream_t s)
 }
 
 // ---- plan cache for the one-shot calls ----
-using Key = std::tuple<int, double, double, int64_t, double, int, int>;
+// One plan per (kind, parameters, degree, tol, precision, device).  Calls with
+// the same key share the plan's workspace, so they are serialised: the host side
+// holds the entry's mutex while it launches, and the launches wait (on the
+// device) for the previous call's work through the entry's event, whatever
+// stream that call used.  Before the workspace may be reallocated for a larger
+// batch, the previous call's work is waited for on the host.
+using Key = std::tuple<int, double, double, double, double, int64_t, double, int, int>;
+struct CacheEntry {
+    thx_plan *p = nullptr;
+    std::mutex mu;
+    hipEvent_t done = nullptr; // recorded after each call's launches
+    ~CacheEntry()
+    {
+        if (done) (void)hipEventDestroy(done);
+        delete p;
+    }
+};
 std::mutex g_cache_mu;
-std::map<Key, thx_plan *> g_cache;
+std::map<Key, std::unique_ptr<CacheEntry>> g_cache;
+
+// true when executing `batch` vectors of `elems` coefficients in all may grow
+// (free and reallocate) a workspace of the plan
+bool may_reallocate(const thx_plan *p, int64_t batch, int64_t elems)
+{
+    if (p->dense) return false;
+    if (p->next && p->tmp_elems < elems) return true;
+    for (const thx_plan *q = p; q; q = q->next)
+        if (q->path != 0 && q->ws_batch < batch) return true;
+    return false;
+}
 
 thx_status cached_convert(thx_kind kind, const double *params, int np, const double *alpha, double *beta,
                           int64_t N, int64_t batch, double tol, thx_precision prec, hipStream_t s)
@@ -1338,26 +1446,53 @@ thx_status cached_convert(thx_kind kind, const double *params, int np, const dou
     if (N < 0) return THX_INVALID_ARGUMENT;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    Key k{(int)kind, np > 0 ? params[0] : 0.0, np > 1 ? params[1] : 0.0, N, tol, (int)prec, dev};
-    thx_plan *p = nullptr;
+    double kp[4] = {0, 0, 0, 0};
+    for (int i = 0; i < np && i < 4; ++i) kp[i] = params[i];
+    const Key k{(int)kind, kp[0], kp[1], kp[2], kp[3], N, tol, (int)prec, dev};
+    CacheEntry *e = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(k);
-        if (it != g_cache.end()) p = it->second;
+        if (it != g_cache.end()) e = it->second.get();
     }
-    if (!p) {
+    if (!e) {
+        thx_plan *p = nullptr;
         thx_status st = create_plan(&p, kind, params, np, N, tol, prec, 0, s);
         if (st != THX_OK && st != THX_TOL_NOT_REACHED) return st;
         std::lock_guard<std::mutex> lk(g_cache_mu);
         auto it = g_cache.find(k);
         if (it != g_cache.end()) {
             delete p;
-            p = it->second;
         } else {
-            g_cache[k] = p;
+            std::unique_ptr<CacheEntry> ne(new (std::nothrow) CacheEntry());
+            if (!ne) {
+                delete p;
+                return THX_OUT_OF_MEMORY;
+            }
+            ne->p = p;
+            hipError_t he = hipEventCreateWithFlags(&ne->done, hipEventDisableTiming);
+            if (he != hipSuccess) {
+                g_last_hip_error = (int)he;
+                return THX_HIP_ERROR;
+            }
+            it = g_cache.emplace(k, std::move(ne)).first;
         }
+        e = it->second.get();
     }
-    return do_execute(p, alpha, beta, N, batch, N + 1, s);
+    std::lock_guard<std::mutex> lk(e->mu);
+    hipError_t he = hipStreamWaitEvent(s, e->done, 0);
+    if (he == hipSuccess && may_reallocate(e->p, batch, batch * (N + 1))) he = hipEventSynchronize(e->done);
+    if (he != hipSuccess) {
+        g_last_hip_error = (int)he;
+        return THX_HIP_ERROR;
+    }
+    const thx_status st = do_execute(e->p, alpha, beta, N, batch, N + 1, s);
+    he = hipEventRecord(e->done, s);
+    if (st == THX_OK && he != hipSuccess) {
+        g_last_hip_error = (int)he;
+        return THX_HIP_ERROR;
+    }
+    return st;
 }
 
 // ---- mixed-degree batches (CSR layout), one plan per FFT-length bucket ----
@@ -1707,7 +1842,7 @@ thx_status thx_plan_fft_geometry(const thx_plan *p, int64_t *rows, int64_t *cols
 double thx_plan_achieved_tol(const thx_plan *p, int part)
 {
     if (!p || part < 0 || part >= p->parts || p->path == 0 || p->path == 4) return -1.0;
-    return p->dfinal[part];
+    return p->dfinal[part] * p->escale[part];
 }
 
 thx_status thx_plan_factors(const thx_plan *p, int part, double *ell, int32_t *pivots, int64_t *n_out,
@@ -1762,10 +1897,39 @@ thx_status thx_lag2lag(const double *alpha, double *beta, int64_t N, int64_t bat
 thx_status thx_cache_clear(void)
 {
     std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto &kv : g_cache) {
+        // wait for a call of another thread that is still launching, then for its work
+        std::lock_guard<std::mutex> le(kv.second->mu);
+        (void)hipEventSynchronize(kv.second->done);
+    }
     if (!g_cache.empty()) (void)hipDeviceSynchronize();
-    for (auto &kv : g_cache) delete kv.second;
     g_cache.clear();
     return THX_OK;
+}
+
+thx_status thx_jac2jac(const double *alpha, double *beta, int64_t N, int64_t batch, double a, double b, double g,
+                       double d, double tol, thx_precision prec, hipStream_t stream)
+{
+    const double p[4] = {a, b, g, d};
+    return cached_convert(THX_JAC2JAC, p, 4, alpha, beta, N, batch, tol, prec, stream);
+}
+thx_status thx_jac2cheb(const double *alpha, double *beta, int64_t N, int64_t batch, double a, double b,
+                        double tol, thx_precision prec, hipStream_t stream)
+{
+    const double p[2] = {a, b};
+    return cached_convert(THX_JAC2CHEB, p, 2, alpha, beta, N, batch, tol, prec, stream);
+}
+thx_status thx_cheb2jac(const double *alpha, double *beta, int64_t N, int64_t batch, double g, double d,
+                        double tol, thx_precision prec, hipStream_t stream)
+{
+    const double p[2] = {g, d};
+    return cached_convert(THX_CHEB2JAC, p, 2, alpha, beta, N, batch, tol, prec, stream);
+}
+
+thx_status thx_execute_varlen(const thx_plan *plan, const double *alpha, double *beta, const int64_t *d_offsets,
+                              int64_t count, int64_t total, int64_t *d_skipped, hipStream_t stream)
+{
+    return do_execute_varlen(plan, alpha, beta, d_offsets, count, total, d_skipped, stream);
 }
 
 thx_status thx_lambda_table(double *out, int64_t count, double z0, hipStream_t stream)
@@ -1876,6 +2040,6 @@ const char *thx_status_string(thx_status s)
     return "THX_UNKNOWN";
 }
 
-int thx_last_hip_error(void) { return g_last_hip_error; }
+hipError_t thx_last_hip_error(void) { return (hipError_t)g_last_hip_error; }
 
 } // extern "C"

@@ -143,3 +143,45 @@ def test_table_rejects_negative_count(lib):
 def test_jacobi_bad_parameters(lib, kind, params):
     st, h = _create(lib, kind, params, 50, 1e-15)
     assert st == 1 and not h.value
+
+
+def test_boundary_calls_declared():
+    # the paper's commands (Sec. 1, 5.1-5.4) and the variable-length execution
+    names = _declared()
+    for must in ["thx_jac2jac", "thx_jac2cheb", "thx_cheb2jac", "thx_execute_varlen", "thx_batch_create",
+                 "thx_plan_achieved_tol", "thx_last_hip_error"]:
+        assert must in names
+
+
+@pytest.mark.parametrize("fname,args", [
+    ("thx_jac2jac", (0.5, 0.5, 0.5, -1.5)),     # parameters must be > -1
+    ("thx_jac2jac", (-1.0, 0.5, 0.5, 0.5)),
+    ("thx_jac2cheb", (-1.5, 0.0)),
+    ("thx_cheb2jac", (0.0, -2.0)),
+])
+def test_jacobi_oneshots_reject_parameters(lib, fname, args):
+    f = getattr(lib, fname)
+    f.restype = ctypes.c_int
+    f.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_double] * (len(args) + 1)
+                  + [ctypes.c_int, ctypes.c_void_p])
+    assert f(None, None, 10, 1, *args, 1e-15, 0, None) == 1
+
+
+def test_oneshot_rejects_negative_degree(lib):
+    lib.thx_jac2cheb.restype = ctypes.c_int
+    lib.thx_jac2cheb.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_int64] * 2 + [ctypes.c_double] * 3
+                                 + [ctypes.c_int, ctypes.c_void_p])
+    assert lib.thx_jac2cheb(None, None, -1, 1, 0.5, -0.25, 1e-15, 0, None) == 1
+
+
+def test_varlen_rejects_bad_arguments(lib):
+    f = lib.thx_execute_varlen
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] * 2 + [ctypes.c_void_p] * 2
+    assert f(None, None, None, None, 3, 10, None, None) == 1     # null plan
+    assert f(None, None, None, None, 0, 0, None, None) == 1      # null plan even with nothing to do
+
+
+def test_last_hip_error_starts_clear(lib):
+    lib.thx_last_hip_error.restype = ctypes.c_int
+    assert lib.thx_last_hip_error() == 0

@@ -1,0 +1,142 @@
+"""GPU tests of the boundary calls beyond plan/execute: the paper's one-shot
+commands jac2jac(v,a,b,g,d), jac2cheb and cheb2jac (Sec. 5.3) through the plan
+cache, their serialisation across streams, and the variable-length execution on
+device offsets.  Bars as in tests/bars.py.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1604_07486_amd import inputs
+
+from . import bars
+from .test_gpu_parity import _dev, _jac_ref, thx  # noqa: F401  (thx: the module fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind,params,N,prec", [
+    (3, (0.0, 0.5 ** 0.5, -0.25, 0.5 ** 0.5), 3000, 0),   # Fig. 7 pair
+    (3, (0.5, -0.25, -0.5, -0.5), 2500, 0),
+    (5, (0.5, -0.25), 2000, 0),
+    (5, (0.5, -0.25), 2000, 1),
+    (6, (0.5, -0.25), 1800, 0),
+    (5, (0.5, -0.25), 255, 0),                              # dense path
+])
+def test_jacobi_oneshots(thx, kind, params, N, prec):
+    import torch
+    print(f"[case] one-shot kind={kind} params={params} N={N} prec={prec}", flush=True)
+    alpha = inputs.coeffs(N, 1.0, seed=N + 3, batch=2)
+    a = _dev(alpha)
+    b = torch.full_like(a, float("nan"))
+    tol = 1e-15 if prec == 0 else 1e-7
+    fn = {3: thx.thx_jac2jac, 5: thx.thx_jac2cheb, 6: thx.thx_cheb2jac}[kind]
+    fn(a, b, *params, tol=tol, prec=prec)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    plan = thx.Plan(kind, N, tol, prec, params=params)
+    c = torch.full_like(a, float("nan"))
+    plan.execute(a, c)
+    torch.cuda.synchronize()
+    assert torch.equal(b, c)          # the cached plan is the plan thx_plan_create makes
+    for i in range(2):
+        bars.check(got[i], _jac_ref(kind, alpha[i], params), alpha[i], 1e-13 if prec == 0 else 5e-6, kind, params,
+                   label=f"vector {i} ")
+    thx.thx_cache_clear()
+
+
+def test_oneshot_serialised_across_streams(thx):
+    # the same cached plan used from two streams, the second call with a larger
+    # batch (its workspace grows): each result matches the plan's own
+    import torch
+    N = 20000
+    alpha = inputs.coeffs(N, 1.0, seed=77, batch=3)
+    a = _dev(alpha)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out1 = torch.full_like(a[:1], float("nan"))
+    out2 = torch.full_like(a, float("nan"))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        thx.thx_leg2cheb(a[:1], out1, stream=s1)
+    with torch.cuda.stream(s2):
+        thx.thx_leg2cheb(a, out2, stream=s2)
+    with torch.cuda.stream(s1):
+        out3 = torch.full_like(a[:1], float("nan"))
+        thx.thx_leg2cheb(a[1:2], out3, stream=s1)
+    torch.cuda.synchronize()
+    # the same plan on the same batch sizes (the partial-sum grouping depends on the batch)
+    plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64)
+    r1, r2, r3 = torch.empty_like(out1), torch.empty_like(out2), torch.empty_like(out3)
+    plan.execute(a[:1], r1)
+    plan.execute(a, r2)
+    plan.execute(a[1:2], r3)
+    torch.cuda.synchronize()
+    assert torch.equal(out1, r1) and torch.equal(out2, r2) and torch.equal(out3, r3)
+    thx.thx_cache_clear()
+
+
+def _varlen_case(thx, kind, params, plan_degree, degrees, prec, seed, extra_bad=()):
+    import torch
+    tol = 1e-15 if prec == 0 else 1e-7
+    plan = thx.Plan(kind, plan_degree, tol, prec, params=params)
+    parts = [inputs.coeffs(int(n), 1.0, seed=seed + i) for i, n in enumerate(degrees)]
+    flat = np.concatenate(parts) if parts else np.zeros(0)
+    offs = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    a = _dev(flat)
+    b = torch.full_like(a, 7.0)
+    skipped = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    plan.execute_varlen(a, b, torch.from_numpy(offs).to("cuda:0"), skipped=skipped)
+    torch.cuda.synchronize()
+    return plan, parts, offs, b.cpu().numpy(), int(skipped.item())
+
+
+@pytest.mark.parametrize("kind,params,plan_degree,prec", [
+    (0, (), 6000, 0),                 # single-workgroup / three-pass FFT
+    (0, (), 6000, 1),
+    (1, (), 30000, 0),                # cheb2leg: row 0 direct per member
+    (5, (0.5, -0.25), 3000, 0),       # two stages through the plan's intermediate
+    (0, (), 300, 0),                  # dense path
+    (2, (1.5, 0.5), 9000, 0),         # unit step (suffix sums)
+])
+def test_execute_varlen(thx, kind, params, plan_degree, prec):
+    rng = inputs.rng(plan_degree + kind)
+    degrees = list(rng.integers(0, plan_degree + 1, 11)) + [plan_degree, 0, plan_degree + 5, 2]
+    print(f"[case] varlen kind={kind} plan degree={plan_degree} prec={prec} degrees={degrees}", flush=True)
+    plan, parts, offs, got, skipped = _varlen_case(thx, kind, params, plan_degree, degrees, prec, seed=5)
+    assert skipped == 1                                  # the member above the plan's degree
+    bar = 1e-13 if prec == 0 else 5e-6
+    for i, al in enumerate(parts):
+        g = got[offs[i]:offs[i + 1]]
+        if len(al) - 1 > plan_degree:
+            assert np.all(g == 7.0)                      # skipped: untouched
+            continue
+        if kind in (3, 5, 6):
+            ref = _jac_ref(kind, al, params)
+        else:
+            ref = oracle.matvec(bars.ORACLE_NAME[kind], al, params)
+        scale = 2 * (len(al) - 1) + 1 if kind == 2 else (None if kind == 5 else 1.0)
+        bars.check(g, ref, al, bar, kind, params, entry_scale=scale, label=f"member {i} n={len(al) - 1} ")
+
+
+def test_execute_varlen_malformed_offsets(thx):
+    # decreasing and out-of-range offsets are skipped and counted; valid members converted
+    import torch
+    N = 3000
+    plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64)
+    al = inputs.coeffs(2000, 1.0, seed=9)
+    a1 = inputs.coeffs(500, 1.0, seed=10)
+    flat = np.concatenate([al, a1])
+    # members [0, 2001) and [2001, 2502) valid; [2502, 2400) decreasing; [2400, 99999) past the end
+    offs = np.array([0, 2001, 2502, 2400, 99999], dtype=np.int64)
+    print(f"[case] varlen malformed offsets {offs.tolist()}", flush=True)
+    a = _dev(flat)
+    b = torch.full_like(a, 7.0)
+    skipped = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    plan.execute_varlen(a, b, torch.from_numpy(offs).to("cuda:0"), skipped=skipped)
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    assert int(skipped.item()) == 2
+    bars.check(got[:2001], oracle.matvec("leg2cheb", al), al, 1e-13, 0, entry_scale=1.0, label="member 0 ")
+    bars.check(got[2001:2502], oracle.matvec("leg2cheb", a1), a1, 1e-13, 0, entry_scale=1.0, label="member 1 ")

@@ -2,9 +2,11 @@
 and the plan's path choices (forced FFT, autotuning, row length, FFT radix,
 slot grouping, fused column pass) drawn together, so that combinations the
 targeted tests do not list are compared with the oracle too.  Same bars as
-test_gpu_parity: 1e-13 (FP64, and FP64 with the single-precision tail) and 5e-6
-(FP32-bulk) of ||alpha||_1, scaled by the largest matrix entry where entries grow
-with the degree.
+test_gpu_parity (tests/bars.py): 1e-13 (FP64, and FP64 with the single-precision
+tail) and 5e-6 (FP32-bulk) of ||alpha||_1, scaled by the largest matrix entry at
+the tested degree where entries grow with the degree, and of the rounding scale
+max_j (|A| |alpha|)_j.  Every kind runs at the same Hankel tolerance, 1e-15
+(FP64) or 1e-7 (FP32-bulk).
 """
 from __future__ import annotations
 
@@ -14,7 +16,8 @@ import pytest
 import oracle
 from paper_1604_07486_amd import inputs
 
-from .test_gpu_parity import _dev, _err, _jac_ref, thx  # noqa: F401  (thx: the module fixture)
+from . import bars
+from .test_gpu_parity import _dev, _jac_ref, thx  # noqa: F401  (thx: the module fixture)
 
 pytestmark = pytest.mark.gpu
 
@@ -51,27 +54,8 @@ def _case(i):
     else:
         params = ()
     if kind in (3, 5, 6):
-        N = min(N, 5000)   # the Jacobi oracle's entries are costly: keep its O(N^2) in seconds
+        N = min(N, bars.DENSE_MAX)   # the composite matrix (for the bar scale) is formed densely
     return kind, params, N, batch, prec, force_fft, tune, env
-
-
-def _jac_scale(kind, N, params):
-    """Largest entry of the stage matrices (up to degree 1000): the bar scales with it."""
-    if kind == 3:
-        a, b, g, d = params
-    elif kind == 5:
-        (a, b), (g, d) = params, (-0.5, -0.5)
-    else:
-        (a, b), (g, d) = (-0.5, -0.5), params
-    n = min(N, 1000)
-    s = 1.0
-    if b != d:
-        s *= max(1.0, oracle.absmax("jac2jac_b", n, (b, a, d)))
-    if a != g:
-        s *= max(1.0, oracle.absmax("jac2jac_b", n, (a, d, g)))
-    if kind == 6:
-        s *= float(np.sqrt(np.pi) / oracle.lambda_table(N)[-1])
-    return s
 
 
 @pytest.mark.parametrize("i", range(CASES))
@@ -83,16 +67,8 @@ def test_random_case(thx, i, monkeypatch):
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     p = 1.5 if kind == 1 else 1.0
-    # Hankel tolerances: D1 and D2 of cheb2leg and of the Jacobi stages amplify the
-    # truncation error (up to ~1e3 of tol for these parameter ranges, measured), so
-    # their parts are factorised further, as a caller of those kinds would
     fp64 = prec != 1
-    if kind == 1:
-        tol = 1e-17 if fp64 else 1e-9
-    elif kind in (3, 5, 6):
-        tol = 1e-16 if fp64 else 1e-10
-    else:
-        tol = 1e-15 if fp64 else 1e-7
+    tol = 1e-15 if fp64 else 1e-7
     alpha = inputs.coeffs(N, p, seed=100 + i, batch=batch)
     plan = thx.Plan(kind, N, tol, prec, params=params, flags=thx.FLAG_FORCE_FFT if force_fft else 0)
     if tune:
@@ -103,21 +79,14 @@ def test_random_case(thx, i, monkeypatch):
     torch.cuda.synchronize()
     got = b.cpu().numpy()
     bar = 1e-13 if fp64 else 5e-6
-    if kind in (3, 5, 6):
-        scale = _jac_scale(kind, N, params)
-    elif kind in (2, 4):
-        name = {2: "ultra2ultra", 4: "lag2lag"}[kind]
-        scale = max(1.0, oracle.absmax(name, N, params))
-    else:
-        scale = 1.0
+    # leg2cheb and cheb2leg: bar relative to ||alpha||_1 as it stands; the others
+    # scaled by their largest entry at this degree
+    scale = 1.0 if kind in (0, 1) else bars.entry_max(kind, N, params)
     for j in range(batch):
         if kind in (3, 5, 6):
             ref = _jac_ref(kind, alpha[j], params)
         else:
             ref = oracle.matvec({0: "leg2cheb", 1: "cheb2leg", 2: "ultra2ultra", 4: "lag2lag"}[kind], alpha[j],
                                 params)
-        err = _err(got[j], ref, alpha[j])
-        print(f"  vector {j}: path={plan.path} K={plan.rank} tail={plan.tail_slots} L={plan.fft_length} "
-              f"err={err:.3e} bar={bar * scale:.3e}", flush=True)
-        assert np.all(np.isfinite(got[j]))
-        assert err < bar * scale, (i, j, err)
+        print(f"  vector {j}: path={plan.path} K={plan.rank} tail={plan.tail_slots} L={plan.fft_length}", flush=True)
+        bars.check(got[j], ref, alpha[j], bar, kind, params, entry_scale=scale, label=f"case {i} vector {j} ")

@@ -331,3 +331,14 @@ def test_pivoted_cholesky_near_best():
         piv, a, ells = oracle.pivoted_cholesky(lambda p: H[:, p], np.diag(H).copy(), 0.0, kmax=K)
         err = np.linalg.norm(H - (ells.T / a) @ ells, 2)
         assert err <= 50 * sv[K]   # best rank-K 2-norm error is sigma_{K+1}
+
+
+@pytest.mark.parametrize("kind,params", [("leg2cheb", ()), ("cheb2leg", ()), ("ultra2ultra", (0.75, 0.25)),
+                                         ("jac2jac_b", (0.5, -0.25, -0.5)), ("lag2lag", (0.5, -0.25))])
+def test_matvec_absolute_matches_dense(kind, params):
+    # the row scales sum_k |A_jk| |alpha_k| used by the error bars
+    N = 60
+    alpha = inputs.coeffs(N, 1.0, seed=41)
+    ref = np.abs(oracle.dense(kind, N, params)) @ np.abs(alpha)
+    got = oracle.matvec(kind, alpha, params, absolute=True)
+    assert np.max(np.abs(got - ref) / ref) < 1e-14
