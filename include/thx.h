@@ -39,7 +39,9 @@ typedef enum {
                                  tol is below the double-precision floor; the
                                  plan is still created and usable                 */
     THX_OUT_OF_MEMORY = 4,    /* device or host allocation failed                  */
-    THX_HIP_ERROR = 5         /* a HIP runtime call failed                         */
+    THX_HIP_ERROR = 5,        /* a HIP runtime call failed                         */
+    THX_WORKSPACE_TOO_LARGE = 6 /* thx_execute_noalloc: the execution needs more
+                                 workspace than the static scratch holds         */
 } thx_status;
 
 typedef enum {
@@ -126,6 +128,24 @@ thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, 
  * degree out of range, ld too small, batch < 0 or above the limit), THX_HIP_ERROR. */
 thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
                        int64_t batch, int64_t ld, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): thx_execute with every
+ * workspace buffer (packed input, FFT intermediates, partial sums, the
+ * intermediates between stages) carved from a static device array of
+ * thx_noalloc_scratch_bytes() = 512 MiB, which the library holds on each GPU it
+ * runs on until the process ends.  The call allocates nothing (no hipMalloc or
+ * hipFree, no events; per-phase timing is not recorded).  Same arguments and
+ * errors as thx_execute, plus THX_WORKSPACE_TOO_LARGE when the execution's
+ * workspace does not fit (the slot chunks shrink before that happens: one
+ * degree-2^20 FP64 vector fits).  Results equal thx_execute's up to rounding
+ * (the chunking of the rank slots, and so the order of the partial sums, may
+ * differ).  Every call on a GPU uses that GPU's one scratch, which keeps the
+ * last call's contents: calls that overlap on one GPU (unordered streams or
+ * threads) race and must be ordered by the caller. */
+thx_status thx_execute_noalloc(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
+                               int64_t batch, int64_t ld, hipStream_t stream);
+int64_t thx_noalloc_scratch_bytes(void);
 
 /* Variable-length members on device offsets (the paper's batches of Sec. 2.1
  * with one factorisation reused for every member): member i occupies

@@ -23,7 +23,7 @@ FP64, FP32_BULK, FP64_TAIL32 = 0, 1, 2
 FLAG_FORCE_DIRECT, FLAG_FORCE_FFT, FLAG_NO_DENSE, FLAG_AUTOTUNE = 1, 2, 4, 8
 PHASES = ["pack", "toep_lds", "col_fwd", "row", "col_inv", "row0", "unpack", "direct", "dense", "scan"]
 STATUS = {0: "THX_OK", 1: "THX_INVALID_ARGUMENT", 2: "THX_UNSUPPORTED", 3: "THX_TOL_NOT_REACHED",
-          4: "THX_OUT_OF_MEMORY", 5: "THX_HIP_ERROR"}
+          4: "THX_OUT_OF_MEMORY", 5: "THX_HIP_ERROR", 6: "THX_WORKSPACE_TOO_LARGE"}
 
 _i64, _i32, _dbl, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -64,6 +64,8 @@ _sig("thx_jac2jac", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, _dbl, 
 _sig("thx_jac2cheb", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
 _sig("thx_cheb2jac", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctypes.c_int, _vp)
 _sig("thx_execute_varlen", ctypes.c_int, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp)
+_sig("thx_execute_noalloc", ctypes.c_int, _vp, _vp, _vp, _i64, _i64, _i64, _vp)
+_sig("thx_noalloc_scratch_bytes", _i64)
 _sig("thx_cache_clear", ctypes.c_int)
 _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
@@ -225,6 +227,19 @@ class Plan:
             raise ValueError("alpha and beta must share shape and row stride, unit column stride")
         _check(_lib.thx_execute(self._h, _ptr(a2), _ptr(b2), N, a2.shape[0], a2.stride(0), _stream(stream)),
                "thx_execute")
+        return beta
+
+    def execute_noalloc(self, alpha, beta, degree=None, stream=None):
+        """thx_execute_noalloc (workspace in the library's static scratch) on [batch][ld] tensors."""
+        _check_tensor(alpha, "alpha")
+        _check_tensor(beta, "beta")
+        N = self.degree if degree is None else degree
+        a2 = alpha if alpha.dim() == 2 else alpha.view(1, -1)
+        b2 = beta if beta.dim() == 2 else beta.view(1, -1)
+        if a2.stride(1) != 1 or b2.stride(1) != 1 or a2.stride(0) != b2.stride(0) or a2.shape != b2.shape:
+            raise ValueError("alpha and beta must share shape and row stride, unit column stride")
+        _check(_lib.thx_execute_noalloc(self._h, _ptr(a2), _ptr(b2), N, a2.shape[0], a2.stride(0),
+                                        _stream(stream)), "thx_execute_noalloc")
         return beta
 
     def execute_varlen(self, alpha, beta, offsets, skipped=None, stream=None):

@@ -13,6 +13,7 @@
 #include "thx_device.hpp"
 #include <math.h>
 #include <algorithm>
+#include <mutex>
 
 namespace thx {
 
@@ -794,6 +795,39 @@ void launch_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nma
     const int nt = 256;
     k_varlen<<<(unsigned)((count + nt - 1) / nt), nt, 0, s>>>(off, count, total, nmax, off2, deg,
                                                                (unsigned long long *)skipped);
+}
+
+// ============================================================================
+// Static scratch of thx_execute_noalloc: every workspace buffer of such an
+// execution is carved from this array, so the call allocates nothing.  Each GPU
+// holds its own copy at its own address; host code must use the address from
+// hipGetSymbolAddress (the array's name is a host-side stand-in).
+// ============================================================================
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+void *scratch_device_ptr(hipError_t *err)
+{
+    static std::mutex mu;
+    static void *ptrs[SCRATCH_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= SCRATCH_MAX_DEVICES)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void *q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)); // with `dev` current: that GPU's copy
+        if (e != hipSuccess || !q) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        ptrs[dev] = q;
+    }
+    *err = hipSuccess;
+    return ptrs[dev];
 }
 
 // ============================================================================

@@ -136,6 +136,13 @@ void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *de
 void launch_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nmax, int64_t *off2, int64_t *deg,
                    int64_t *skipped, hipStream_t s);
 
+// ---- static scratch (thx_execute_noalloc) -------------------------------------------
+constexpr int64_t SCRATCH_BYTES = (int64_t)512 << 20; // held on every GPU the library runs on
+constexpr int SCRATCH_MAX_DEVICES = 64;
+// The current device's copy of the scratch (hipGetSymbolAddress once per device,
+// with that device current); nullptr and *err set on failure.
+void *scratch_device_ptr(hipError_t *err);
+
 // ---- direct O(N^2) ----------------------------------------------------------------
 void launch_direct(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                    int64_t ld, double *beta, int64_t N, int64_t batch, const double *tsym,

@@ -24,6 +24,7 @@ using namespace thx;
 namespace {
 
 thread_local int g_last_hip_error = 0;
+thread_local bool g_no_timing = false; // thx_execute_noalloc records no events
 
 struct HipFail {
     hipError_t e;
@@ -772,8 +773,10 @@ thx_status create_ultra(thx_plan **out, const double *pv, int64_t degree, double
     });
 }
 
+struct Scratch;
 void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems);
+                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems,
+                  const Scratch *sc = nullptr);
 
 // Materialise the matrix of a plan whose stages all run the direct evaluation:
 // row k of the identity goes through them and comes out as column k of A, so
@@ -943,7 +946,7 @@ struct PhaseTimer {
     hipEvent_t a = nullptr, b = nullptr;
     PhaseTimer(thx_plan *p_, int ph, hipStream_t s_) : p(p_), s(s_), phase(ph)
     {
-        if (!((p->timing >> ph) & 1u) || p->marks.size() >= MAX_MARKS) return;
+        if (g_no_timing || !((p->timing >> ph) & 1u) || p->marks.size() >= MAX_MARKS) return;
         const size_t need = 2 * (p->marks.size() + 1);
         while (p->ev_pool.size() < need) {
             hipEvent_t e;
@@ -961,6 +964,48 @@ struct PhaseTimer {
         p->marks.push_back({phase, a, b});
     }
 };
+
+// Workspace of one stage's execution: the plan's own buffers (grown on demand
+// by ensure_workspace) or a layout carved from the library's static scratch
+// (thx_execute_noalloc).
+struct Ws {
+    void *X = nullptr, *U = nullptr, *Wp = nullptr;
+    double *row0 = nullptr, *row0_part = nullptr, *sfx_tot = nullptr;
+    int64_t U_slots = 0;
+};
+Ws own_ws(const thx_plan *p)
+{
+    Ws w;
+    w.X = p->X;
+    w.U = p->U;
+    w.Wp = p->Wp;
+    w.row0 = p->row0;
+    w.row0_part = p->row0_part;
+    w.sfx_tot = p->sfx_tot;
+    w.U_slots = p->U_slots;
+    return w;
+}
+
+// Partial-sum groups of an execution of `batch` vectors with slot chunks of
+// `us` (the three-pass path) -- the count run_slots produces.
+int64_t groups_for(const thx_plan *p, int64_t batch, int64_t us)
+{
+    if (p->S <= 0) return 1;
+    if (p->path == 1) {
+        const int64_t Gt = std::min<int64_t>(p->S, std::max<int64_t>(1, (p->lds_blocks + batch - 1) / batch));
+        const int64_t spg = (p->S + Gt - 1) / Gt;
+        return (p->S + spg - 1) / spg;
+    }
+    const int64_t tiles = p->geom.L1 / p->geom.TC;
+    int64_t G = 0;
+    for (int64_t s0 = 0; s0 < p->S; s0 += us) {
+        const int64_t ns = std::min<int64_t>(us, p->S - s0);
+        int64_t Gc = std::min<int64_t>(ns, std::max<int64_t>(1, (p->p3_blocks + tiles * batch - 1) / (tiles * batch)));
+        const int64_t spg = (ns + Gc - 1) / Gc;
+        G += (ns + spg - 1) / spg;
+    }
+    return G;
+}
 
 void ensure_workspace(thx_plan *p, int64_t batch)
 {
@@ -1016,14 +1061,14 @@ int p1_slots_per_block(const thx_plan *p, int ns, int64_t batch)
 // into its partial sums; returns the number of partial-sum groups.  Phases are
 // timed on `tm` (the plan the caller executes).
 template <typename T>
-int run_slots(thx_plan *p, thx_plan *tm, const int64_t *off, const int64_t *deg, const double *alpha, int64_t N,
-              int64_t batch, int64_t ld, hipStream_t s)
+int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const int64_t *deg, const double *alpha,
+              int64_t N, int64_t batch, int64_t ld, hipStream_t s)
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
     {
         PhaseTimer t(tm, THX_PHASE_PACK, s);
-        launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, p->X, p->ncs, s);
+        launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, w.X, p->ncs, s);
     }
     int G = 0;
     if (p->S > 0) {
@@ -1032,28 +1077,28 @@ int run_slots(thx_plan *p, thx_plan *tm, const int64_t *off, const int64_t *deg,
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
             PhaseTimer t(tm, THX_PHASE_TOEP_LDS, s);
-            if (!launch_toep_lds<T>(p->L, p->lds_radix, p->X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL,
-                                    p->Wp, batch, s))
+            if (!launch_toep_lds<T>(p->L, p->lds_radix, w.X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL,
+                                    w.Wp, batch, s))
                 throw HipFail{hipErrorInvalidValue};
         } else {
             const MultiPassGeom &g = p->geom;
             const int64_t tiles = g.L1 / g.TC;
-            for (int s0 = 0; s0 < p->S; s0 += (int)p->U_slots) {
-                const int ns = (int)std::min<int64_t>(p->U_slots, p->S - s0);
+            for (int s0 = 0; s0 < p->S; s0 += (int)w.U_slots) {
+                const int ns = (int)std::min<int64_t>(w.U_slots, p->S - s0);
                 if (p->fuse_p1 && g.L2 <= 4) {
                     PhaseTimer t(tm, THX_PHASE_ROW, s);
-                    if (!launch_mp_p2f<T>(g, p->X, p->ncs, n, ell, s0, ns, p->U, batch, p->that, p->twL1, p->twA,
+                    if (!launch_mp_p2f<T>(g, w.X, p->ncs, n, ell, s0, ns, w.U, batch, p->that, p->twL1, p->twA,
                                           p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
                 } else {
                     {
                         PhaseTimer t(tm, THX_PHASE_COL_FWD, s);
-                        if (!launch_mp_p1<T>(g, p->X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch),
-                                             nullptr, p->U, batch, p->twL2, p->twA, s))
+                        if (!launch_mp_p1<T>(g, w.X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch),
+                                             nullptr, w.U, batch, p->twL2, p->twA, s))
                             throw HipFail{hipErrorInvalidValue};
                     }
                     PhaseTimer t(tm, THX_PHASE_ROW, s);
-                    if (!launch_mp_p2<T>(g, p->U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
+                    if (!launch_mp_p2<T>(g, w.U, ns, batch, p->that, p->twL1, p->twA, p->twL2, true, nullptr, 1.0, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
                 int Gc = (int)std::min<int64_t>(
@@ -1062,42 +1107,53 @@ int run_slots(thx_plan *p, thx_plan *tm, const int64_t *off, const int64_t *deg,
                 Gc = (ns + spg - 1) / spg;
                 {
                     PhaseTimer t(tm, THX_PHASE_COL_INV, s);
-                    if (!launch_mp_p3<T>(g, p->U, p->ncs, n, ell, s0, ns, spg, Gc, p->Wp, G, batch, p->twL2, s))
+                    if (!launch_mp_p3<T>(g, w.U, p->ncs, n, ell, s0, ns, spg, Gc, w.Wp, G, batch, p->twL2, s))
                         throw HipFail{hipErrorInvalidValue};
                 }
                 G += Gc;
             }
         }
     } else {
-        launch_zero(p->Wp, (int64_t)(p->esize() * (size_t)(batch * p->ncs)), s);
+        launch_zero(w.Wp, (int64_t)(p->esize() * (size_t)(batch * p->ncs)), s);
         G = 1;
     }
     return G;
 }
 
 template <typename T>
-void execute_fft(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                 int64_t N, int64_t batch, int64_t ld, hipStream_t s)
+void execute_fft(thx_plan *p, const Ws &w, const Ws &wt, const int64_t *off, const int64_t *deg,
+                 const double *alpha, double *beta, int64_t N, int64_t batch, int64_t ld, hipStream_t s)
 {
-    const int G = run_slots<T>(p, p, off, deg, alpha, N, batch, ld, s);
+    const int G = run_slots<T>(p, w, p, off, deg, alpha, N, batch, ld, s);
     thx_plan *t = p->tail_on ? p->tail : nullptr;
-    const int G2 = t ? run_slots<float>(t, p, off, deg, alpha, N, batch, ld, s) : 0;
+    const int G2 = t ? run_slots<float>(t, wt, p, off, deg, alpha, N, batch, ld, s) : 0;
     const double *row0 = nullptr;
     if (p->row0_direct) {
         PhaseTimer tm(p, THX_PHASE_ROW0, s);
-        launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, p->row0_part, p->row0, s);
-        row0 = p->row0;
+        launch_row0_direct(p->kd, off, deg, alpha, ld, N, batch, p->tsym, p->hk, w.row0_part, w.row0, s);
+        row0 = w.row0;
     }
     {
         PhaseTimer tm(p, THX_PHASE_UNPACK, s);
-        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, p->Wp, G, t ? t->Wp : nullptr, G2, p->ncs,
+        launch_unpack<T>(p->kd, off, deg, alpha, ld, beta, N, batch, w.Wp, G, t ? wt.Wp : nullptr, G2, p->ncs,
                          p->L, p->alias, p->tsym, row0, s);
     }
     launch_check();
 }
 
+// A static scratch region handed to one execution (thx_execute_noalloc):
+// intermediates between stages first, then one region every stage reuses in
+// turn (the stages run one after another on the stream).
+struct Scratch {
+    char *base = nullptr;
+    int64_t bytes = 0;
+    double *tmp = nullptr, *tmp2 = nullptr;
+    char *region = nullptr;
+    int64_t region_bytes = 0;
+};
+
 void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s);
+                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s, const Scratch *sc = nullptr);
 
 void ensure_tmp(thx_plan *p, int64_t elems)
 {
@@ -1116,7 +1172,7 @@ void ensure_tmp(thx_plan *p, int64_t elems)
 // plans go through the plan's intermediate buffer of `tmp_elems` doubles
 // (laid out like alpha).
 void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems)
+                  int64_t degree, int64_t batch, int64_t ld, hipStream_t s, int64_t tmp_elems, const Scratch *sc)
 {
     if (p->dense) {
         PhaseTimer t(p, THX_PHASE_DENSE, s);
@@ -1126,27 +1182,79 @@ void execute_core(thx_plan *p, const int64_t *off, const int64_t *deg, const dou
         return;
     }
     if (!p->next) {
-        execute_stage(p, off, deg, alpha, beta, degree, batch, ld, s);
+        execute_stage(p, off, deg, alpha, beta, degree, batch, ld, s, sc);
         return;
     }
-    ensure_tmp(p, tmp_elems);
-    double *bufs[2] = {p->tmp, p->tmp2};
+    if (!sc) ensure_tmp(p, tmp_elems);
+    double *bufs[2] = {sc ? sc->tmp : p->tmp, sc ? sc->tmp2 : p->tmp2};
     const double *in = alpha;
     int k = 0;
     for (thx_plan *q = p; q; q = q->next) {
         double *out = q->next ? bufs[(k++) & 1] : beta;
-        execute_stage(q, off, deg, in, out, degree, batch, ld, s);
+        execute_stage(q, off, deg, in, out, degree, batch, ld, s, sc);
         in = out;
     }
 }
 
-void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
-                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s)
+// ---- layouts in the static scratch (thx_execute_noalloc) ----
+constexpr int64_t SC_ALIGN = 256;
+inline int64_t sc_round(int64_t b) { return (b + SC_ALIGN - 1) / SC_ALIGN * SC_ALIGN; }
+
+// Carve one stage's workspace (and its single-precision tail's) from `region`
+// with slot chunks of at most `chunk`; returns the bytes used (ws written when
+// `out` is set).
+int64_t carve_stage(const thx_plan *p, int64_t batch, int64_t chunk, char *region, Ws *w, Ws *wt)
 {
-    if (p->path == 4 && degree >= 2) {
+    int64_t used = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        char *q = region ? region + used : nullptr;
+        used += sc_round(std::max<int64_t>(bytes, 1));
+        return q;
+    };
+    Ws a, b;
+    if (p->path == 4) {
+        a.sfx_tot = (double *)take(16 * batch * suffix_chunks(p->kd, p->N));
+    } else if (p->path == 1 || p->path == 2) {
+        auto one = [&](const thx_plan *q, Ws &x) {
+            const int64_t es = (int64_t)q->esize();
+            x.U_slots = q->path == 2 ? std::max<int64_t>(1, std::min<int64_t>(chunk, std::max(q->S, 1))) : 0;
+            x.X = take(es * batch * q->ncs);
+            x.Wp = take(es * groups_for(q, batch, std::max<int64_t>(x.U_slots, 1)) * batch * q->ncs);
+            if (q->path == 2) x.U = take(es * q->L * batch * x.U_slots);
+        };
+        one(p, a);
+        a.row0 = (double *)take(8 * batch);
+        if (p->row0_direct) a.row0_part = (double *)take(8 * batch * ROW0_PMAX);
+        if (p->tail_on && p->tail) one(p->tail, b);
+    }
+    if (w) *w = a;
+    if (wt) *wt = b;
+    return used;
+}
+
+// Largest slot chunk whose layout fits `bytes`; 0 when none does.
+int64_t fit_chunk(const thx_plan *p, int64_t batch, int64_t bytes)
+{
+    const int64_t smax = std::max<int64_t>(1, std::max(p->S, p->tail ? p->tail->S : 0));
+    for (int64_t c = smax; c >= 1; --c)
+        if (carve_stage(p, batch, c, nullptr, nullptr, nullptr) <= bytes) return c;
+    return 0;
+}
+
+void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const double *alpha, double *beta,
+                   int64_t degree, int64_t batch, int64_t ld, hipStream_t s, const Scratch *sc)
+{
+    Ws w, wt;
+    if (sc) {
+        carve_stage(p, batch, fit_chunk(p, batch, sc->region_bytes), sc->region, &w, &wt);
+    } else if (p->path != 0 && degree >= 2) {
         ensure_workspace(p, batch);
+        w = own_ws(p);
+        if (p->tail) wt = own_ws(p->tail);
+    }
+    if (p->path == 4 && degree >= 2) {
         PhaseTimer t(p, THX_PHASE_SCAN, s);
-        launch_suffix(p->kd, off, deg, alpha, ld, beta, degree, batch, p->tsym, p->hk, p->sfx_tot, s);
+        launch_suffix(p->kd, off, deg, alpha, ld, beta, degree, batch, p->tsym, p->hk, w.sfx_tot, s);
         launch_check();
         return;
     }
@@ -1156,9 +1264,8 @@ void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const do
         launch_check();
         return;
     }
-    ensure_workspace(p, batch);
-    if (p->prec == THX_FP64) execute_fft<double>(p, off, deg, alpha, beta, degree, batch, ld, s);
-    else execute_fft<float>(p, off, deg, alpha, beta, degree, batch, ld, s);
+    if (p->prec == THX_FP64) execute_fft<double>(p, w, wt, off, deg, alpha, beta, degree, batch, ld, s);
+    else execute_fft<float>(p, w, wt, off, deg, alpha, beta, degree, batch, ld, s);
 }
 
 thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int64_t degree, int64_t batch,
@@ -1178,6 +1285,59 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
         return THX_OUT_OF_MEMORY;
     }
     return THX_OK;
+}
+
+// Execution with every workspace buffer in the static scratch: intermediates
+// between stages first, then one region the stages use in turn.  Allocates
+// nothing and records no events.
+thx_status do_execute_noalloc(const thx_plan *cp, const double *alpha, double *beta, int64_t degree,
+                              int64_t batch, int64_t ld, hipStream_t s)
+{
+    thx_plan *p = const_cast<thx_plan *>(cp);
+    if (!p || degree < 0 || degree > p->N || batch < 0 || ld < degree + 1) return THX_INVALID_ARGUMENT;
+    if (batch == 0) return THX_OK;
+    if (!alpha || !beta) return THX_INVALID_ARGUMENT;
+    if (batch > 65535 && !p->dense) return THX_INVALID_ARGUMENT;
+    hipError_t he = hipSuccess;
+    char *base = (char *)scratch_device_ptr(&he);
+    if (!base) {
+        g_last_hip_error = (int)he;
+        return THX_HIP_ERROR;
+    }
+    Scratch sc;
+    sc.base = base;
+    sc.bytes = SCRATCH_BYTES;
+    int64_t used = 0;
+    if (p->next && !p->dense) {
+        if (batch > (SCRATCH_BYTES / 8) / ld) return THX_WORKSPACE_TOO_LARGE;
+        const int64_t tb = sc_round(8 * batch * ld);
+        int stages = 0;
+        for (const thx_plan *q = p; q; q = q->next) ++stages;
+        sc.tmp = (double *)(base + used);
+        used += tb;
+        if (stages >= 3) {
+            sc.tmp2 = (double *)(base + used);
+            used += tb;
+        }
+        if (used > SCRATCH_BYTES) return THX_WORKSPACE_TOO_LARGE;
+    }
+    sc.region = base + used;
+    sc.region_bytes = SCRATCH_BYTES - used;
+    if (!p->dense && degree >= 2)
+        for (const thx_plan *q = p; q; q = q->next)
+            if (q->path != 0 && fit_chunk(q, batch, sc.region_bytes) == 0) return THX_WORKSPACE_TOO_LARGE;
+    g_no_timing = true;
+    thx_status st = THX_OK;
+    try {
+        execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s, batch * ld, &sc);
+    } catch (const HipFail &f) {
+        g_last_hip_error = (int)f.e;
+        st = THX_HIP_ERROR;
+    } catch (const std::bad_alloc &) {
+        st = THX_OUT_OF_MEMORY;
+    }
+    g_no_timing = false;
+    return st;
 }
 
 // Variable-length execution: members at device offsets, degrees derived on the
@@ -1926,6 +2086,14 @@ thx_status thx_cheb2jac(const double *alpha, double *beta, int64_t N, int64_t ba
     return cached_convert(THX_CHEB2JAC, p, 2, alpha, beta, N, batch, tol, prec, stream);
 }
 
+thx_status thx_execute_noalloc(const thx_plan *plan, const double *alpha, double *beta, int64_t degree,
+                               int64_t batch, int64_t ld, hipStream_t stream)
+{
+    return do_execute_noalloc(plan, alpha, beta, degree, batch, ld, stream);
+}
+
+int64_t thx_noalloc_scratch_bytes(void) { return SCRATCH_BYTES; }
+
 thx_status thx_execute_varlen(const thx_plan *plan, const double *alpha, double *beta, const int64_t *d_offsets,
                               int64_t count, int64_t total, int64_t *d_skipped, hipStream_t stream)
 {
@@ -2036,6 +2204,7 @@ const char *thx_status_string(thx_status s)
     case THX_TOL_NOT_REACHED: return "THX_TOL_NOT_REACHED";
     case THX_OUT_OF_MEMORY: return "THX_OUT_OF_MEMORY";
     case THX_HIP_ERROR: return "THX_HIP_ERROR";
+    case THX_WORKSPACE_TOO_LARGE: return "THX_WORKSPACE_TOO_LARGE";
     }
     return "THX_UNKNOWN";
 }

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_status_strings(lib):
     lib.thx_status_string.restype = ctypes.c_char_p
     for code, name in enumerate(["THX_OK", "THX_INVALID_ARGUMENT", "THX_UNSUPPORTED", "THX_TOL_NOT_REACHED",
-                                 "THX_OUT_OF_MEMORY", "THX_HIP_ERROR"]):
+                                 "THX_OUT_OF_MEMORY", "THX_HIP_ERROR", "THX_WORKSPACE_TOO_LARGE"]):
         assert lib.thx_status_string(code).decode() == name
 
 
@@ -185,3 +185,11 @@ def test_varlen_rejects_bad_arguments(lib):
 def test_last_hip_error_starts_clear(lib):
     lib.thx_last_hip_error.restype = ctypes.c_int
     assert lib.thx_last_hip_error() == 0
+
+
+def test_noalloc_rejects_null_plan_and_states_scratch(lib):
+    lib.thx_execute_noalloc.restype = ctypes.c_int
+    lib.thx_execute_noalloc.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64] * 3 + [ctypes.c_void_p]
+    assert lib.thx_execute_noalloc(None, None, None, 10, 1, 11, None) == 1
+    lib.thx_noalloc_scratch_bytes.restype = ctypes.c_int64
+    assert lib.thx_noalloc_scratch_bytes() == 512 << 20
