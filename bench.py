@@ -41,7 +41,7 @@ def parse():
                     help="run only the headline timed loop (for profiler runs)")
     ap.add_argument("--prec", choices=["fp64", "fp32", "tail32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
-    ap.add_argument("--only", choices=["batched", "config5", "sweep"], default=None,
+    ap.add_argument("--only", choices=["batched", "config5", "sweep", "config1"], default=None,
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
@@ -57,6 +57,7 @@ def parse():
 COPY_BYTES = 512 << 20
 MFMA_FP64_TFLOPS = 78.6   # MI355X dense matrix-core peaks
 MFMA_BF16_TFLOPS = 2500.0
+VALU_FP64_TFLOPS = 78.6   # 256 CUs x 128 FP64 flops per clock (FMA = 2) x 2.4 GHz
 
 # Measured HBM traffic of the dominant kernel (row pass of the headline plan),
 # valid only for the device sources it was taken with, the same template
@@ -266,6 +267,39 @@ def sampled_error(oracle, kind, alpha, got, rows):
     return float(np.max(np.abs(got[rows] - ref)) / np.sum(np.abs(alpha)))
 
 
+def lds_flops(S, L, nc, batch=1):
+    """Algorithmic flops of one single-workgroup launch: per slot and vector a forward and an
+    inverse complex FFT of length L (5 L log2 L each), the product with the symbol (6 L), the
+    scaling of the input by the Cholesky column (2 nc) and the scaled accumulation (4 nc)."""
+    import math
+    return batch * S * (10 * L * math.log2(L) + 6 * L + 6 * nc)
+
+
+def run_config1(thx, torch, inputs, oracle, dev, steps):
+    """Legendre -> Chebyshev, one vector of degree 2048, FP64, Hankel tol 1e-15: one launch of the
+    single-workgroup FFT path per conversion; its rate against the FP64 vector peak."""
+    N = 2048
+    alpha = inputs.coeffs(N, 1.0, seed=2048)
+    a = torch.from_numpy(alpha).to(dev)
+    b = torch.empty_like(a)
+    plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64, flags=thx.FLAG_FORCE_FFT)
+    plan.autotune(1)
+    reps = max(200, steps * 10)
+    ms, tim = time_plan(thx, torch, plan, a, b, reps, 20, phase="toep_lds")
+    err = float(np.max(np.abs(b.cpu().numpy() - oracle.matvec("leg2cheb", alpha))) / np.sum(np.abs(alpha)))
+    tot, cnt = tim["toep_lds"]
+    kms = tot / cnt
+    fl = lds_flops(plan.rank, plan.fft_length, N // 2 + 1)
+    tf = fl / (kms * 1e-3) / 1e12
+    return {"workload": "leg2cheb N=2048 (2049 coefficients), batch 1, FP64, alpha_k ~ N(0,1)(k+1)^-1 seed 2048, "
+                        "Hankel tol 1e-15, FFT path (length 2048 complex per parity half), plan autotuned",
+            "ms_per_conversion": round(ms, 5), "coeffs_per_s": round((N + 1) / (ms * 1e-3), 1),
+            "K": plan.rank, "L": plan.fft_length, "lds_radix": plan.lds_radix, "max_err_over_l1": err,
+            "roofline": {"kernel": "toep_lds", "bound": "alu", "achieved": round(tf, 3),
+                         "peak": VALU_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / VALU_FP64_TFLOPS, 5),
+                         "flops_per_launch": int(fl), "avg_launch_ms": round(kms, 5), "launches": cnt}}
+
+
 def run_sweep(thx, torch, inputs, oracle, dev, steps):
     """Precision sweep of Legendre -> Chebyshev: FP64 (Hankel tol 1e-15) against FP32-bulk (1e-7)
     at N = 2^12, 2^16, 2^20, 2^22 for coefficients decaying like (k+1)^-2 and undecayed; error
@@ -407,7 +441,11 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
                 elif n <= 4096:
                     e = np.max(np.abs(gi - oracle.jac2cheb(al, *params))) / np.sum(np.abs(al))
                 else:
-                    e = None
+                    # degree 2^18: the oracle's sampled-row route (unit step of the first
+                    # parameter by its bidiagonal factor, then the reflected stage on the rows)
+                    r = inputs.sample_rows(n, 64, seed=i)
+                    ref = oracle.jac2cheb_rows(al, *params, r)
+                    e = np.max(np.abs(gi[r] - ref)) / np.sum(np.abs(al))
                 if e is not None:
                     worst = max(worst, float(e))
             conf5[f"{kname}_{pname}"] = {"coeffs_per_s": round(bt.coefficients / (ms5 * 1e-3), 1),
@@ -467,6 +505,8 @@ def main():
             res = run_batched(thx, torch, inputs, oracle, dev, args.steps, precs=precs)
         elif args.only == "sweep":
             res = {"precision_sweep": run_sweep(thx, torch, inputs, oracle, dev, args.steps)}
+        elif args.only == "config1":
+            res = {"config1": run_config1(thx, torch, inputs, oracle, dev, args.steps)}
         else:
             kinds = (args.kind,) if args.kind else ("ultra", "jac2cheb")
             res = run_config5(thx, torch, inputs, oracle, dev, args.steps, kinds=kinds, precs=precs)
@@ -536,13 +576,14 @@ def main():
     del plant
 
     # ---- Chebyshev -> Legendre at the same N (Sec. 5.1) ----
-    planc = thx.Plan(thx.CHEB2LEG, N, 1e-17, thx.FP64)
+    planc = thx.Plan(thx.CHEB2LEG, N, 1e-15, thx.FP64)
     planc.autotune(1)
     msc, _ = time_plan(thx, torch, planc, a, b, max(5, args.steps // 2), 2)
     errc = sampled_error(oracle, "cheb2leg", alpha, b.cpu().numpy(), rows)
     Kc = planc.rank
     del planc
 
+    conf1 = run_config1(thx, torch, inputs, oracle, dev, args.steps)
     batch_res = run_batched(thx, torch, inputs, oracle, dev, args.steps)
     conf5 = run_config5(thx, torch, inputs, oracle, dev, args.steps)
     sweep = run_sweep(thx, torch, inputs, oracle, dev, args.steps)
@@ -603,11 +644,12 @@ def main():
                       "K": K32, "max_err_over_l1": err32, "bar": 5e-6, "hankel_tol": 1e-7,
                       "phases_ms_avg": phase_avg(tim32)},
         "fp64_tail32": tail32,
+        "config1": conf1,
         "batched": batch_res,
         "config5": conf5,
         "precision_sweep": sweep,
         "cheb2leg_fp64": {"coeffs_per_s": round((N + 1) / (msc * 1e-3), 1), "ms_per_step": round(msc, 5),
-                          "K": Kc, "max_err_over_l1": errc, "hankel_tol": 1e-17},
+                          "K": Kc, "max_err_over_l1": errc, "hankel_tol": 1e-15},
     }
     print(json.dumps(out), flush=True)
 
