@@ -45,9 +45,13 @@ def parse():
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
-    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DB", "WRITE_DB", "RUN_LOG"), default=None,
-                    help="summarise two rocprofv3 --pmc runs of --headline-only --copy-calibration "
-                         "(FETCH_SIZE, WRITE_SIZE) into " + "profiles/<...>.txt and exit (no GPU use)")
+    ap.add_argument("--write-traffic", nargs="+", metavar="ARG", default=None,
+                    help="FETCH_DB WRITE_DB RUN_LOG [OUT]: summarise two rocprofv3 --pmc runs of "
+                         "--headline-only --copy-calibration (FETCH_SIZE, WRITE_SIZE) into OUT (default: the "
+                         "FP64 row-pass file under profiles/) and exit (no GPU use)")
+    ap.add_argument("--write-trace", nargs=4, metavar=("DB", "OUT_MD", "TITLE", "COMMAND"), default=None,
+                    help="summarise the timed region of a rocprofv3 --kernel-trace database (the kernels "
+                         "between the trace markers 1 and 2) into a markdown table and exit (no GPU use)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 512 MiB (bandwidth ceiling and the "
                          "reference for HBM byte counters)")
@@ -62,7 +66,7 @@ VALU_FP64_TFLOPS = 78.6   # 256 CUs x 128 FP64 flops per clock (FMA = 2) x 2.4 G
 # Measured HBM traffic of the dominant kernel (row pass of the headline plan),
 # valid only for the device sources it was taken with, the same template
 # instantiation (row length) and the same algorithmic bytes per launch.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "row_pass_leg2cheb_N2p20_fp64_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "passes_leg2cheb_N2p20_fp64_hbm_traffic.txt")
 TRAFFIC_SOURCES = ["paper_1604_07486_amd/csrc/kernels.hip", "paper_1604_07486_amd/csrc/fft_reg.hpp",
                    "paper_1604_07486_amd/csrc/thx_device.hpp", "paper_1604_07486_amd/csrc/launch.hpp"]
 
@@ -112,7 +116,7 @@ def source_digest():
 
 
 def pmc_dispatches(db, counter):
-    """(kernel name, value in KiB) per dispatch of one rocprofv3 --pmc database."""
+    """(kernel name, value in KiB) per dispatch of one rocprofv3 --pmc database, in dispatch order."""
     import re
     import sqlite3
     con = sqlite3.connect(db)
@@ -122,48 +126,81 @@ def pmc_dispatches(db, counter):
     return [(re.sub(r"\(.*", "", k).replace("void ", "").replace("thx::", ""), v) for _, k, v in rows]
 
 
-def write_traffic(fetch_db, write_db, run_log):
-    """Average FETCH_SIZE / WRITE_SIZE of the execute dispatches of the row pass, scaled by what the
-    same counters read for the 512 MiB device copy of the same run.  `run_log` holds the JSON line
-    of the profiled `--headline-only` run: the row-pass instantiation it executed and that launch's
-    algorithmic bytes."""
+def kernel_phase(name):
+    """Phase of a library kernel by its name (None for kernels outside the execution)."""
+    for prefix, phase in (("k_mp_p1", "col_fwd"), ("k_mp_p2f", "row"), ("k_mp_p2<", "row"), ("k_mp_p3", "col_inv"),
+                          ("k_toep_lds", "toep_lds"), ("k_pack", "pack"), ("k_unpack", "unpack")):
+        if name.startswith(prefix):
+            return phase
+    return None
+
+
+def timed_window(d):
+    """The dispatches between trace marker 1 and the next marker 2 (the timed loop)."""
+    marks = [i for i, (k, _) in enumerate(d) if k.startswith("k_trace_marker")]
+    return d[marks[0] + 1:marks[1]]
+
+
+def write_traffic(fetch_db, write_db, run_log, out=None):
+    """FETCH_SIZE / WRITE_SIZE per dispatch of every kernel of the timed loop, scaled by what the
+    same counters read for the 512 MiB device copy of the same run, against each launch's
+    algorithmic bytes.  `run_log` holds the JSON line of the profiled `--headline-only` run (its
+    precision, row-pass instantiation and the algorithmic bytes of each phase).  The key lines
+    below the table describe the row pass (read back by the bench for `roofline.traffic`)."""
     info = None
     for line in open(run_log):
         if line.startswith("{") and '"headline_only"' in line:
             info = json.loads(line)
-    kernel, algo = info["row_kernel"], info["row_bytes_per_launch"]
-    out = {}
+    prec, algo_by_phase, lg = info["prec"], info["phase_bytes"], info.get("log2n", 20)
+    out = out or TRAFFIC_FILE
+    per = {}
     for key, db, counter in (("fetch", fetch_db, "FETCH_SIZE"), ("write", write_db, "WRITE_SIZE")):
         d = pmc_dispatches(db, counter)
-        row = [v for k, v in d if k == kernel]
-        big = max(row)
-        row = [v for v in row if v > 0.5 * big]           # drops the plan's symbol transform
         copy = max(v for k, v in d if "copyBuffer" in k)   # the 512 MiB calibration copy
-        out[key] = (sum(row) / len(row), len(row), (COPY_BYTES / 1024) / copy)
-    traffic = out["fetch"][0] * 1024 * out["fetch"][2] + out["write"][0] * 1024 * out["write"][2]
+        factor = (COPY_BYTES / 1024) / copy
+        for k, v in timed_window(d):
+            per.setdefault(k, {}).setdefault(key, []).append(v)
+        per.setdefault("_factor", {})[key] = factor
+    fac = per.pop("_factor")
+    rows_md, row = [], None
+    for k, vals in sorted(per.items(), key=lambda kv: -sum(kv[1].get("fetch", [0]))):
+        f = sum(vals["fetch"]) / len(vals["fetch"]) * 1024 * fac["fetch"]
+        w = sum(vals["write"]) / len(vals["write"]) * 1024 * fac["write"]
+        ph = kernel_phase(k)
+        algo = algo_by_phase.get(ph) if ph else None
+        ratio = f"{(f + w) / algo:.3f}" if algo else "-"
+        rows_md.append(f"# | `{k}` | {ph or '-'} | {len(vals['fetch'])} | {f / 1e6:.1f} | {w / 1e6:.1f} | "
+                       f"{(algo or 0) / 1e6:.1f} | {ratio} |")
+        if ph == "row" and (row is None or f + w > row[1] + row[2]):
+            row = (k, f, w, algo, vals)
+    cmd = ("rocprofv3 --pmc {c} -d $OUT/pmc/{p}_{lg}_{c} -o pmc -- python3 $R/bench.py --headline-only --steps 3 "
+           "--warmup 1 --copy-calibration --prec {p} --log2n {lg}")
     lines = [
-        f"# HBM traffic of the row pass ({kernel}), leg2cheb N=2^20 FP64 headline plan",
+        f"# HBM traffic per launch of the timed loop, leg2cheb N=2^{lg} {prec} plan (autotuned for one vector)",
         "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
-        "# execute dispatches; factors = bytes of the 512 MiB device copy in the same run / counter.",
-        "# Commands (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp):",
-        "#   rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/fp64_FETCH_SIZE -o pmc -- python3 $R/bench.py "
-        "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
-        "#   rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/fp64_WRITE_SIZE -o pmc -- python3 $R/bench.py "
-        "--headline-only --steps 3 --warmup 1 --copy-calibration --prec fp64",
-        "#   python3 bench.py --write-traffic $OUT/pmc/fp64_FETCH_SIZE/pmc_results.db "
-        "$OUT/pmc/fp64_WRITE_SIZE/pmc_results.db $OUT/pmc/fp64_FETCH_SIZE.log",
-        f"kernel = {kernel}",
+        "# dispatches between trace markers 1 and 2; factors = bytes of the 512 MiB device copy in the",
+        "# same run / counter.  Commands (repo root $R, output directory $OUT, from /tmp, TMPDIR=/tmp):",
+        "#   " + cmd.format(c="FETCH_SIZE", p=prec, lg=lg) + f" > $OUT/pmc/{prec}_{lg}_FETCH_SIZE.log",
+        "#   " + cmd.format(c="WRITE_SIZE", p=prec, lg=lg),
+        f"#   python3 bench.py --write-traffic $OUT/pmc/{prec}_{lg}_FETCH_SIZE/pmc_results.db "
+        f"$OUT/pmc/{prec}_{lg}_WRITE_SIZE/pmc_results.db $OUT/pmc/{prec}_{lg}_FETCH_SIZE.log "
+        f"{os.path.relpath(out, ROOT)}",
+        f"# fetch factor {fac['fetch']:.4f}, write factor {fac['write']:.4f}",
+        "# | kernel | phase | launches | read (MB) | written (MB) | algorithmic (MB) | measured / algorithmic |",
+        "# |---|---|---:|---:|---:|---:|---:|",
+        *rows_md,
+        f"kernel = {row[0]}",
         "phase = row",
-        f"fetch_kib_per_dispatch = {out['fetch'][0]:.1f}",
-        f"write_kib_per_dispatch = {out['write'][0]:.1f}",
-        f"dispatches = {out['fetch'][1]}",
-        f"fetch_factor = {out['fetch'][2]:.4f}",
-        f"write_factor = {out['write'][2]:.4f}",
-        f"traffic_bytes_per_launch = {traffic:.0f}",
-        f"algorithmic_bytes_per_launch = {algo}",
+        f"fetch_kib_per_dispatch = {sum(row[4]['fetch']) / len(row[4]['fetch']):.1f}",
+        f"write_kib_per_dispatch = {sum(row[4]['write']) / len(row[4]['write']):.1f}",
+        f"dispatches = {len(row[4]['fetch'])}",
+        f"fetch_factor = {fac['fetch']:.4f}",
+        f"write_factor = {fac['write']:.4f}",
+        f"traffic_bytes_per_launch = {row[1] + row[2]:.0f}",
+        f"algorithmic_bytes_per_launch = {row[3]}",
         f"source_sha256 = {source_digest()}",
     ]
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -228,21 +265,60 @@ def time_plan(thx, torch, plan, a, b, steps, warmup, phase=None):
     """Milliseconds per execution over `steps` timed executions.  With `phase`,
     that phase's launches are bracketed by HIP events inside the timed loop (two
     events per launch: the other phases run without markers, which would add a
-    few microseconds each)."""
+    few microseconds each).  Trace markers 1 and 2 (empty kernels, outside the
+    timed region) delimit the loop in a kernel trace."""
     for _ in range(warmup):
         plan.execute(a, b)
     torch.cuda.synchronize()
     plan.timings(reset=True)
     if phase is not None:
         plan.enable_timing(True, phases=(phase,))
+    thx.thx_trace_marker(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.execute(a, b)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    thx.thx_trace_marker(2)
     plan.enable_timing(False)
     return (t1 - t0) * 1e3 / steps, plan.timings(reset=True)
+
+
+def write_trace(db, out_md, title, command):
+    """Markdown table of the kernels between the first trace marker 1 and the next marker 2 of a
+    rocprofv3 --kernel-trace database (the timed loop only: no plan, tuning or warm-up dispatches),
+    with the loop's span against the sum of its kernel durations (gaps between launches)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end, grid_x from kernels order by start").fetchall()
+    con.close()
+    marks = [(i, gx) for i, (n, _, _, gx) in enumerate(rows) if "k_trace_marker" in n]
+    i0 = next(i for i, gx in marks if gx == 64)
+    i1 = next(i for i, gx in marks if gx == 128 and i > i0)
+    win = [r for r in rows[i0 + 1:i1] if "k_trace_marker" not in r[0]]
+    stats = {}
+    for n, st, en, _ in win:
+        name = n.split("(")[0].replace("void ", "")
+        stats.setdefault(name, []).append((en - st) / 1e3)
+    total = sum(sum(v) for v in stats.values())
+    span = (max(r[2] for r in win) - min(r[1] for r in win)) / 1e3
+    lines = [f"# Kernel trace: {title}", "",
+             "Command (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp), then the summary:", "",
+             "```", command,
+             f"python3 $R/bench.py --write-trace <kt_results.db> <this file> \"{title}\" \"<the command>\"",
+             "```", "",
+             f"Only the dispatches of the timed loop (between trace markers 1 and 2): {len(win)} launches, "
+             f"{total:.1f} us of kernel time in a span of {span:.1f} us "
+             f"({100 * (span - total) / span:.1f}% of the span outside kernels).", "",
+             "| kernel | calls | total (us) | average (us) | min (us) | max (us) | % |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {len(v)} | {sum(v):.1f} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
+                     f"{max(v):.1f} | {100 * sum(v) / total:.1f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def phase_breakdown(torch, plan, a, b, steps):
@@ -347,11 +423,14 @@ def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bul
             bt.execute(ab, bb, graph=True)
         torch.cuda.synchronize()
         reps = max(3, steps // 5)
+        thx.thx_trace_marker(1)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
             bt.execute(ab, bb, graph=True)
         torch.cuda.synchronize()
         bms = (time.perf_counter() - t0) * 1e3 / reps
+        thx.thx_trace_marker(2)
         got = bb.cpu().numpy()
         g = inputs.rng(5)
         worst = 0.0
@@ -423,11 +502,14 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
                 bt.execute(a5, b5, graph=True)
             torch.cuda.synchronize()
             reps = max(3, steps // 5)
+            thx.thx_trace_marker(1)
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(reps):
                 bt.execute(a5, b5, graph=True)
             torch.cuda.synchronize()
             ms5 = (time.perf_counter() - t0) * 1e3 / reps
+            thx.thx_trace_marker(2)
             got = b5.cpu().numpy()
             worst = 0.0
             for i in list(range(0, 65536, 8191)) + [65536, 65599]:
@@ -466,6 +548,9 @@ def main():
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return
+    if args.write_trace:
+        write_trace(*args.write_trace)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this library runs on a single GPU; --gpus must be 1 "
@@ -490,11 +575,15 @@ def main():
         parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
         es = 8 if prec == thx.FP32_BULK else 16
-        row_bytes = phase_bytes("row", es, plan.rank, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
-        print(json.dumps({"headline_only": True, "prec": args.prec, "ms_per_step": ms, "copy_gbs": copy_gbs,
-                          "K": plan.rank, "L": plan.fft_length, "row_ms_avg": phase_avg(tim).get("row"),
+        S = plan.rank - plan.tail_slots
+        pb = {ph: phase_bytes(ph, es, S, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
+              for ph in ("col_fwd", "row", "col_inv")}
+        print(json.dumps({"headline_only": True, "prec": args.prec, "log2n": args.log2n, "ms_per_step": ms,
+                          "copy_gbs": copy_gbs, "K": plan.rank, "tail_slots": plan.tail_slots, "L": plan.fft_length,
+                          "row_ms_avg": phase_avg(tim).get("row"),
                           "row_kernel": row_kernel_name(plan) if prec == thx.FP64 else None,
-                          "row_bytes_per_launch": row_bytes, "phases_ms_avg": phase_avg(parts)}), flush=True)
+                          "row_bytes_per_launch": pb["row"], "phase_bytes": pb,
+                          "phases_ms_avg": phase_avg(parts)}), flush=True)
         return
 
     import oracle

@@ -352,6 +352,12 @@ enum {
 thx_status thx_plan_enable_timing(thx_plan *plan, uint32_t phases);
 thx_status thx_plan_timings(thx_plan *plan, double *ms, int64_t *launches, int reset);
 
+/* Tracing: launch an empty kernel (k_trace_marker) of `id` workgroups of 64
+ * threads on `stream`, 1 <= id <= 65535, so that a kernel trace can be cut
+ * into regions (the trace shows the grid size id * 64).  THX_INVALID_ARGUMENT
+ * outside that range. */
+thx_status thx_trace_marker(int id, hipStream_t stream);
+
 const char *thx_status_string(thx_status s);
 /* hipError_t of the last failed HIP call made by this thread inside the library */
 hipError_t thx_last_hip_error(void);

@@ -66,6 +66,7 @@ _sig("thx_cheb2jac", ctypes.c_int, _vp, _vp, _i64, _i64, _dbl, _dbl, _dbl, ctype
 _sig("thx_execute_varlen", ctypes.c_int, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp)
 _sig("thx_execute_noalloc", ctypes.c_int, _vp, _vp, _vp, _i64, _i64, _i64, _vp)
 _sig("thx_noalloc_scratch_bytes", _i64)
+_sig("thx_trace_marker", ctypes.c_int, ctypes.c_int, _vp)
 _sig("thx_cache_clear", ctypes.c_int)
 _sig("thx_lambda_table", ctypes.c_int, _vp, _i64, _dbl, _vp)
 _sig("thx_gamma_ratio_table", ctypes.c_int, _vp, _i64, _dbl, _dbl, _dbl, _vp)
@@ -364,6 +365,11 @@ def thx_gamma_ratio_table(out, a, b, z0=0.0, stream=None):
     _check_tensor(out, "out")
     _check(_lib.thx_gamma_ratio_table(_ptr(out), out.numel(), z0, a, b, _stream(stream)), "thx_gamma_ratio_table")
     return out
+
+
+def thx_trace_marker(marker_id: int, stream=None):
+    """Empty kernel with marker_id workgroups of 64 threads (cuts kernel traces into regions)."""
+    return _check(_lib.thx_trace_marker(int(marker_id), _stream(stream)), "thx_trace_marker")
 
 
 def thx_status_string(s: int) -> str:

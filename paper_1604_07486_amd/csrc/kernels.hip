@@ -772,6 +772,11 @@ void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *de
     k_row0_sum<<<(unsigned)batch, ROW0_PMAX, 0, s>>>(k, part, (int)P, row0);
 }
 
+// An empty kernel that marks a point in a kernel trace (its grid has `id`
+// workgroups of 64 threads, so the trace shows id * 64 as the grid size).
+__global__ void k_trace_marker() {}
+void launch_trace_marker(int id, hipStream_t s) { k_trace_marker<<<(unsigned)id, 64, 0, s>>>(); }
+
 // Per-member degrees of a variable-length execution from device offsets:
 // member i is alpha[off[i] .. off[i+1]-1].  Members that are malformed, reach
 // beyond `total` or exceed the plan's degree are skipped (degree -1, nothing

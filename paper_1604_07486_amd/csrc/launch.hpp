@@ -136,6 +136,9 @@ void launch_row0_direct(const KindDesc &k, const int64_t *off, const int64_t *de
 void launch_varlen(const int64_t *off, int64_t count, int64_t total, int64_t nmax, int64_t *off2, int64_t *deg,
                    int64_t *skipped, hipStream_t s);
 
+// empty kernel k_trace_marker with `id` workgroups of 64 threads (trace regions)
+void launch_trace_marker(int id, hipStream_t s);
+
 // ---- static scratch (thx_execute_noalloc) -------------------------------------------
 constexpr int64_t SCRATCH_BYTES = (int64_t)512 << 20; // held on every GPU the library runs on
 constexpr int SCRATCH_MAX_DEVICES = 64;

@@ -2094,6 +2094,18 @@ thx_status thx_execute_noalloc(const thx_plan *plan, const double *alpha, double
 
 int64_t thx_noalloc_scratch_bytes(void) { return SCRATCH_BYTES; }
 
+thx_status thx_trace_marker(int id, hipStream_t stream)
+{
+    if (id < 1 || id > 65535) return THX_INVALID_ARGUMENT;
+    launch_trace_marker(id, stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return THX_HIP_ERROR;
+    }
+    return THX_OK;
+}
+
 thx_status thx_execute_varlen(const thx_plan *plan, const double *alpha, double *beta, const int64_t *d_offsets,
                               int64_t count, int64_t total, int64_t *d_skipped, hipStream_t stream)
 {
