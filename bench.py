@@ -41,7 +41,7 @@ def parse():
                     help="run only the headline timed loop (for profiler runs)")
     ap.add_argument("--prec", choices=["fp64", "fp32", "tail32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
-    ap.add_argument("--only", choices=["batched", "config5", "sweep", "config1"], default=None,
+    ap.add_argument("--only", choices=["batched", "config5", "sweep", "config1", "dense"], default=None,
                     help="run one secondary section only (profiler runs) and print its JSON")
     ap.add_argument("--kind", choices=["ultra", "jac2cheb"], default=None,
                     help="with --only config5: one conversion only")
@@ -450,24 +450,29 @@ def run_batched(thx, torch, inputs, oracle, dev, steps, precs=("fp64", "fp32_bul
     return batch_res
 
 
-def dense_alone(thx, torch, a5, b5, prec, tolh, params, steps):
-    """The 65536 degree-255 members alone through one dense plan (matrix cores): time per
-    product, useful flops (the upper triangle: (n+1)(n+2)/2 multiply-adds per vector) against
-    the matrix-core peak the form runs on, and alpha + beta bytes against HBM."""
+def dense_alone(thx, torch, dev, prec, tolh, steps, kind=None, params=(0.5, -0.25)):
+    """65536 vectors of degree 255 through one dense plan (matrix cores): the config-5 Jacobi
+    (1/2, -1/4) -> Chebyshev members, whose two-stage conversion is materialised as one matrix.
+    Time per product (trace markers 1 and 2 around the timed loop), useful flops (the upper
+    triangle: (n+1)(n+2)/2 multiply-adds per vector) against the matrix-core peak the form runs
+    on, and alpha + beta bytes against HBM."""
     n, m = 255, 65536
-    plan = thx.Plan(thx.ULTRA2ULTRA, n, tolh, prec, params=params)
+    kind = thx.JAC2CHEB if kind is None else kind
+    plan = thx.Plan(kind, n, tolh, prec, params=params)
     if plan.path != 3:
         return None
-    a = a5[:m * (n + 1)].view(m, n + 1)
-    b = b5[:m * (n + 1)].view(m, n + 1)
+    a = torch.from_numpy(np.random.default_rng(7).standard_normal((m, n + 1))).to(dev)
+    b = torch.empty_like(a)
     for _ in range(3):
         plan.execute(a, b)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = max(10, steps)
+    thx.thx_trace_marker(1)
     e0.record()
     for _ in range(reps):
         plan.execute(a, b)
     e1.record()
+    thx.thx_trace_marker(2)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     flops = m * (n + 1) * (n + 2)
@@ -475,7 +480,8 @@ def dense_alone(thx, torch, a5, b5, prec, tolh, params, steps):
     peak = MFMA_FP64_TFLOPS if prec == thx.FP64 else MFMA_BF16_TFLOPS / 8
     tf = flops / (ms * 1e-3) / 1e12
     return {"ms": round(ms, 4), "useful_tflops": round(tf, 2), "peak_tflops": peak,
-            "frac_of_peak": round(tf / peak, 4), "hbm_gbs": round(2 * m * (n + 1) * 8 / (ms * 1e-3) / 1e9, 1)}
+            "frac_of_peak": round(tf / peak, 4), "hbm_gbs": round(2 * m * (n + 1) * 8 / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(2 * m * (n + 1) * 8 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2cheb"),
@@ -534,8 +540,8 @@ def run_config5(thx, torch, inputs, oracle, dev, steps, kinds=("ultra", "jac2che
                                          "ms_per_batch": round(ms5, 4), "buckets": bt.buckets(),
                                          "max_err_over_l1_sampled": worst}
             del bt
-            if short == "ultra":
-                conf5[f"dense_alone_{pname}"] = dense_alone(thx, torch, a5, b5, prec, tolh, params, steps)
+            if short == "jac2cheb":
+                conf5[f"dense_alone_{pname}"] = dense_alone(thx, torch, dev, prec, tolh, steps)
     conf5["workload"] = ("65536 vectors of degree 255 + 64 of degree 2^18 in one batch (CSR), alpha_k ~ "
                          "N(0,1)(k+1)^-1 seed 55, hipGraph replay, buckets autotuned; ultraspherical errors "
                          "divided by the entry growth 2N+1; Jacobi checked on the degree-255 members")
@@ -596,6 +602,11 @@ def main():
             res = {"precision_sweep": run_sweep(thx, torch, inputs, oracle, dev, args.steps)}
         elif args.only == "config1":
             res = {"config1": run_config1(thx, torch, inputs, oracle, dev, args.steps)}
+        elif args.only == "dense":
+            prec = thx.FP64 if precs[0] == "fp64" else thx.FP32_BULK
+            res = {"dense_alone": dense_alone(thx, torch, dev, prec, 1e-15 if prec == thx.FP64 else 1e-7, args.steps)}
+            if args.copy_calibration:
+                res["copy_gbs"] = copy_bandwidth(torch)
         else:
             kinds = (args.kind,) if args.kind else ("ultra", "jac2cheb")
             res = run_config5(thx, torch, inputs, oracle, dev, args.steps, kinds=kinds, precs=precs)

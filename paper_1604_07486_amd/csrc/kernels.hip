@@ -1073,10 +1073,60 @@ int suffix_chunks(const KindDesc &k, int64_t N)
     return (int)((nl + SC_CH - 1) / SC_CH);
 }
 
+// Short vectors (at most SS_LANES lanes): one wave per vector, one launch.  Lane
+// q of the vector goes to thread q % 64 in run q / 64 (coalesced loads and
+// stores).  The runs are taken from the last down: each is reverse-scanned by
+// wave shuffles and gets the total of the later runs as a carry (fixed order:
+// deterministic); the next run's values are loaded while the current one is
+// scanned.
+constexpr int SS_NT = 256;
+
+__global__ __launch_bounds__(SS_NT) void k_suffix_small(KindDesc k, VecRef vr, const double *alpha, int64_t ld,
+                                                       double *beta, int64_t N0, int64_t batch,
+                                                       const double *tsym, const double *hk)
+{
+    const int t = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * (SS_NT / 64) + (threadIdx.x >> 6);
+    if (b >= batch) return; // uniform over the wave
+    int64_t base, N;
+    vec_of(vr, b, ld, N0, base, N);
+    if (N < 0) return;
+    const int64_t nl = k.parity ? N / 2 + 1 : N + 1;
+    const int R = (int)((nl + 63) / 64);
+    const double *al = alpha + base;
+    double *be = beta + base;
+    const double g = tsym[0] * hk[0];
+    double cx = 0.0, cy = 0.0;
+    Pair u = sc_lane(k, al, N, (int64_t)(R - 1) * 64 + t);
+    for (int i = R - 1; i >= 0; --i) {
+        const Pair nxt = i > 0 ? sc_lane(k, al, N, (int64_t)(i - 1) * 64 + t) : Pair{0.0, 0.0};
+        const double sx = wave_suffix(u.x), sy = wave_suffix(u.y);
+        const double vx = sx + cx, vy = sy + cy;
+        const int64_t q = (int64_t)i * 64 + t;
+        if (k.parity) {
+            const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+            if (j0 <= N) be[j0] = d1_of(k, j0) * g * vx;
+            if (j1 <= N) be[j1] = d1_of(k, j1) * g * vy;
+        } else if (q <= N) {
+            be[q] = d1_of(k, q) * g * vx;
+        }
+        cx += __shfl(sx, 0, 64);
+        cy += __shfl(sy, 0, 64);
+        u = nxt;
+    }
+}
+
+bool suffix_small(const KindDesc &k, int64_t N) { return (k.parity ? N / 2 + 1 : N + 1) <= SS_LANES; }
+
 void launch_suffix(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha, int64_t ld,
                    double *beta, int64_t N, int64_t batch, const double *tsym, const double *hk, double *tot,
                    hipStream_t s)
 {
+    if (suffix_small(k, N)) {
+        const int64_t blocks = (batch + SS_NT / 64 - 1) / (SS_NT / 64);
+        k_suffix_small<<<(unsigned)blocks, SS_NT, 0, s>>>(k, VecRef{off, deg}, alpha, ld, beta, N, batch, tsym, hk);
+        return;
+    }
     const int nchunk = suffix_chunks(k, N);
     dim3 grid((unsigned)nchunk, (unsigned)batch);
     k_suffix_tot<<<grid, SC_NT, 0, s>>>(k, VecRef{off, deg}, alpha, ld, N, tot, nchunk);

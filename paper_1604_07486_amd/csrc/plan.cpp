@@ -24,6 +24,10 @@ using namespace thx;
 namespace {
 
 thread_local int g_last_hip_error = 0;
+
+// internal plan flags (above the public THX_FLAG_* bits)
+constexpr uint32_t FLAG_IN_CHAIN = 1u << 30; // a stage of a multi-stage conversion
+constexpr uint32_t FLAG_SHORT = 1u << 29;    // a batch's bucket of short members: direct evaluation
 thread_local bool g_no_timing = false; // thx_execute_noalloc records no events
 
 struct HipFail {
@@ -750,7 +754,8 @@ thx_status create_jacobi(thx_plan **out, thx_kind kind, const double *pv, int64_
     // case 3 (a + b <= -1) runs with row 0 computed directly, case 1 (integer
     // steps up) with the banded Toeplitz factor
     return create_chain(out, st.size(), [&](size_t i, thx_plan **o) {
-        return create_single(o, kind, pv, &st[i], degree, tol, prec, flags, s);
+        return create_single(o, kind, pv, &st[i], degree, tol, prec, flags | (st.size() > 1 ? FLAG_IN_CHAIN : 0u),
+                             s);
     });
 }
 
@@ -769,7 +774,8 @@ thx_status create_ultra(thx_plan **out, const double *pv, int64_t degree, double
     st.push_back({l, pv[1]});
     return create_chain(out, st.size(), [&](size_t i, thx_plan **o) {
         const double q[4] = {st[i].first, st[i].second, 0.0, 0.0};
-        return create_single(o, THX_ULTRA2ULTRA, q, nullptr, degree, tol, prec, flags, s);
+        return create_single(o, THX_ULTRA2ULTRA, q, nullptr, degree, tol, prec,
+                             flags | (st.size() > 1 ? FLAG_IN_CHAIN : 0u), s);
     });
 }
 
@@ -905,14 +911,19 @@ thx_status create_single(thx_plan **out, thx_kind kind, const double *pv, const 
     p->row0_direct = (kind == THX_CHEB2LEG) || (jac && jac_case3(*jac));
     try {
         build_tables(p, s);
-        const bool direct = (flags & THX_FLAG_FORCE_DIRECT) ||
+        const bool direct = (flags & (THX_FLAG_FORCE_DIRECT | FLAG_SHORT)) ||
                             (!(flags & THX_FLAG_FORCE_FFT) && degree <= direct_crossover()) ||
                             degree < 2 || p->kd.band >= 0;
         // a parameter lowered by exactly 1: T and H constant (case 1 by suffix sums)
         const bool unit = !p->row0_direct && p->kd.band < 0 &&
                           ((jac && jac->a - jac->g == 1.0) ||
                            ((kind == THX_ULTRA2ULTRA || kind == THX_LAG2LAG) && pv[0] - pv[1] == 1.0));
-        if (direct) {
+        // a conversion that is one unit step takes the O(N) suffix sums at every
+        // degree (short vectors: one wave each), unless the caller asks for the
+        // direct evaluation; inside a chain, short vectors stay direct so that the
+        // whole chain can be materialised as one dense matrix
+        const bool unit_first = unit && degree >= 2 && !(flags & (FLAG_IN_CHAIN | THX_FLAG_FORCE_DIRECT));
+        if (direct && !unit_first) {
             p->path = 0;
             hip_check(hipStreamSynchronize(s));
         } else if (unit) {
@@ -1268,6 +1279,13 @@ void execute_stage(thx_plan *p, const int64_t *off, const int64_t *deg, const do
     else execute_fft<float>(p, w, wt, off, deg, alpha, beta, degree, batch, ld, s);
 }
 
+// plans whose launches have no per-vector grid limit: the dense product, and a
+// single unit step on short vectors (one wave per vector)
+bool unlimited_batch(const thx_plan *p, int64_t degree)
+{
+    return p->dense || (p->path == 4 && !p->next && suffix_small(p->kd, degree));
+}
+
 thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int64_t degree, int64_t batch,
                       int64_t ld, hipStream_t s)
 {
@@ -1275,7 +1293,7 @@ thx_status do_execute(const thx_plan *cp, const double *alpha, double *beta, int
     if (!p || degree < 0 || degree > p->N || batch < 0 || ld < degree + 1) return THX_INVALID_ARGUMENT;
     if (batch == 0) return THX_OK;
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
-    if (batch > 65535 && !p->dense) return THX_INVALID_ARGUMENT; // grid.y / grid.z limit of the launches
+    if (batch > 65535 && !unlimited_batch(p, degree)) return THX_INVALID_ARGUMENT; // grid.y limit of the launches
     try {
         execute_core(p, nullptr, nullptr, alpha, beta, degree, batch, ld, s, batch * ld);
     } catch (const HipFail &f) {
@@ -1297,7 +1315,7 @@ thx_status do_execute_noalloc(const thx_plan *cp, const double *alpha, double *b
     if (!p || degree < 0 || degree > p->N || batch < 0 || ld < degree + 1) return THX_INVALID_ARGUMENT;
     if (batch == 0) return THX_OK;
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
-    if (batch > 65535 && !p->dense) return THX_INVALID_ARGUMENT;
+    if (batch > 65535 && !unlimited_batch(p, degree)) return THX_INVALID_ARGUMENT;
     hipError_t he = hipSuccess;
     char *base = (char *)scratch_device_ptr(&he);
     if (!base) {
@@ -1349,7 +1367,7 @@ thx_status do_execute_varlen(const thx_plan *cp, const double *alpha, double *be
     if (!p || count < 0 || total < 0 || (count > 0 && !d_off)) return THX_INVALID_ARGUMENT;
     if (count == 0) return THX_OK;
     if (!alpha || !beta) return THX_INVALID_ARGUMENT;
-    if (count > 65535 && !p->dense) return THX_INVALID_ARGUMENT; // grid.y limit of the launches
+    if (count > 65535 && !unlimited_batch(p, p->N)) return THX_INVALID_ARGUMENT; // grid.y limit
     try {
         if (count > p->vl_count) {
             dfree(p->vl_off);
@@ -1773,8 +1791,27 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
             // the dense product has no per-vector grid limit: one bucket
             int64_t gmax = 0;
             for (int64_t i : idx) gmax = std::max(gmax, degrees[i]);
-            const bool dense = kv.first == 0 && !(flags & THX_FLAG_NO_DENSE) && gmax + 1 <= DENSE_MAX;
-            const size_t chunk = dense ? idx.size() : (size_t)MAX_BUCKET_MEMBERS;
+            // with autotuning, an FFT bucket keeps its FFT plan and may still pick the dense product
+            const uint32_t f = (kv.first == 0 ? FLAG_SHORT
+                                              : ((flags & THX_FLAG_AUTOTUNE) ? 0u : THX_FLAG_FORCE_FFT)) |
+                               (flags & THX_FLAG_NO_DENSE);
+            // more members than one grid dimension holds: one bucket if the plan for the
+            // whole group has no per-vector grid limit, else chunks of MAX_BUCKET_MEMBERS
+            thx_plan *whole = nullptr;
+            size_t chunk = (size_t)MAX_BUCKET_MEMBERS;
+            if (idx.size() > chunk) {
+                thx_status st = create_plan(&whole, kind, params, nparams, gmax, tol, prec, f, s);
+                if (st != THX_OK && st != THX_TOL_NOT_REACHED) {
+                    delete b;
+                    return st;
+                }
+                if (unlimited_batch(whole, gmax)) {
+                    chunk = idx.size();
+                } else {
+                    delete whole;
+                    whole = nullptr;
+                }
+            }
             for (size_t c0 = 0; c0 < idx.size(); c0 += chunk) {
                 const size_t c1 = std::min(idx.size(), c0 + chunk);
                 thx_batch::Bucket bk;
@@ -1785,11 +1822,13 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                     bk.Nmax = std::max(bk.Nmax, degrees[idx[m]]);
                 }
                 bk.members = (int64_t)ho.size();
-                // with autotuning, an FFT bucket keeps its FFT plan and may still pick the dense product
-                const uint32_t f = (kv.first == 0 ? THX_FLAG_FORCE_DIRECT
-                                                  : ((flags & THX_FLAG_AUTOTUNE) ? 0u : THX_FLAG_FORCE_FFT)) |
-                                   (flags & THX_FLAG_NO_DENSE);
-                thx_status st = create_plan(&bk.plan, kind, params, nparams, bk.Nmax, tol, prec, f, s);
+                thx_status st = THX_OK;
+                if (whole) {
+                    bk.plan = whole; // the group's plan, made above at its largest degree
+                    whole = nullptr;
+                } else {
+                    st = create_plan(&bk.plan, kind, params, nparams, bk.Nmax, tol, prec, f, s);
+                }
                 if (st == THX_TOL_NOT_REACHED) result = st;
                 else if (st != THX_OK) {
                     delete b;
@@ -1803,7 +1842,7 @@ thx_status batch_create(thx_batch **out, thx_kind kind, const double *params, in
                         return ts;
                     }
                 }
-                if (!bk.plan->dense && bk.members > MAX_BUCKET_MEMBERS) {
+                if (!unlimited_batch(bk.plan, bk.Nmax) && bk.members > MAX_BUCKET_MEMBERS) {
                     delete bk.plan;
                     delete b;
                     return THX_UNSUPPORTED;
@@ -1909,10 +1948,12 @@ thx_status batch_execute(thx_batch *b, const double *alpha, double *beta, int us
 // ---------------------------------------------------------------------------
 extern "C" {
 
+constexpr uint32_t PUBLIC_FLAGS = THX_FLAG_FORCE_DIRECT | THX_FLAG_FORCE_FFT | THX_FLAG_NO_DENSE | THX_FLAG_AUTOTUNE;
+
 thx_status thx_plan_create(thx_plan **out, thx_kind kind, const double *params, int nparams, int64_t degree,
                            double tol, thx_precision prec, uint32_t flags, hipStream_t stream)
 {
-    return create_plan(out, kind, params, nparams, degree, tol, prec, flags, stream);
+    return create_plan(out, kind, params, nparams, degree, tol, prec, flags & PUBLIC_FLAGS, stream);
 }
 
 thx_status thx_execute(const thx_plan *plan, const double *alpha, double *beta, int64_t degree, int64_t batch,
@@ -2176,7 +2217,7 @@ thx_status thx_batch_create(thx_batch **out, thx_kind kind, const double *params
                             const int64_t *degrees, int64_t count, double tol, thx_precision prec,
                             uint32_t flags, hipStream_t stream)
 {
-    return batch_create(out, kind, params, nparams, degrees, count, tol, prec, flags, stream);
+    return batch_create(out, kind, params, nparams, degrees, count, tol, prec, flags & PUBLIC_FLAGS, stream);
 }
 
 thx_status thx_batch_execute(thx_batch *batch, const double *alpha, double *beta, int use_graph,
