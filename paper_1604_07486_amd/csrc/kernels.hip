@@ -1357,8 +1357,19 @@ __global__ __launch_bounds__(DB_NT) void k_dense_bf16(const v4u *__restrict__ Bp
     v4u br[BL];
     auto fetch = [&](int kc) {
         const int64_t k0 = (int64_t)DB_KC * kc + 8 * g;
+        if (k0 + 7 <= an && ((abase + k0) & 1) == 0) {
+            // the lane's eight values inside the vector and 16-byte aligned: four 16-byte loads
+            const double2 *p = reinterpret_cast<const double2 *>(alpha + abase + k0);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) xr[i] = k0 + i <= an ? alpha[abase + k0 + i] : 0.0;
+            for (int i = 0; i < 4; ++i) {
+                const double2 v = p[i];
+                xr[2 * i] = v.x;
+                xr[2 * i + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xr[i] = k0 + i <= an ? alpha[abase + k0 + i] : 0.0;
+        }
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
             const int u = (int)threadIdx.x + DB_NT * e; // (part, column, k group)
