@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--write-trace", nargs=4, metavar=("DB", "OUT_MD", "TITLE", "COMMAND"), default=None,
                     help="summarise the timed region of a rocprofv3 --kernel-trace database (the kernels "
                          "between the trace markers 1 and 2) into a markdown table and exit (no GPU use)")
+    ap.add_argument("--write-counters", nargs=4, metavar=("DB", "OUT_MD", "TITLE", "COMMAND"), default=None,
+                    help="average every counter of a rocprofv3 --pmc database per kernel over the dispatches "
+                         "between trace markers 1 and 2 into a markdown table and exit (no GPU use)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain device copy of 512 MiB (bandwidth ceiling and the "
                          "reference for HBM byte counters)")
@@ -201,6 +204,44 @@ def write_traffic(fetch_db, write_db, run_log, out=None):
         f"source_sha256 = {source_digest()}",
     ]
     with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def write_counters(db, out_md, title, command):
+    """Per kernel of the timed loop (between trace markers 1 and 2): the average of every counter the
+    run collected, per dispatch (rocprofv3 reports per-SE and per-SIMD counters summed over the chip)."""
+    import re
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection "
+                       "order by dispatch_id").fetchall()
+    con.close()
+    disp = {}
+    for d, k, c, v in rows:
+        disp.setdefault(d, [re.sub(r"\(.*", "", k).replace("void ", "").replace("thx::", ""), {}])[1][c] = v
+    ids = sorted(disp)
+    marks = [i for i in ids if disp[i][0].startswith("k_trace_marker")]
+    agg = {}
+    for i in ids:
+        if not (marks[0] < i < marks[1]):
+            continue
+        name, cs = disp[i]
+        a = agg.setdefault(name, {"_n": 0})
+        a["_n"] += 1
+        for c, v in cs.items():
+            a[c] = a.get(c, 0.0) + v
+    counters = sorted({c for a in agg.values() for c in a if c != "_n"})
+    lines = [f"# Counters: {title}", "", "Command (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp), "
+             "then the summary:", "", "```", command,
+             f"python3 $R/bench.py --write-counters <pmc_results.db> <this file> \"{title}\" \"<the command>\"",
+             "```", "", "Average per dispatch of the timed loop (between trace markers 1 and 2).", "",
+             "| kernel | dispatches | " + " | ".join(counters) + " |",
+             "|---|---:|" + "---:|" * len(counters)]
+    for name, a in agg.items():
+        n = a["_n"]
+        lines.append(f"| `{name}` | {n} | " + " | ".join(f"{a.get(c, 0.0) / n:.0f}" for c in counters) + " |")
+    with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -556,6 +597,9 @@ def main():
         return
     if args.write_trace:
         write_trace(*args.write_trace)
+        return
+    if args.write_counters:
+        write_counters(*args.write_counters)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
