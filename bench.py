@@ -49,9 +49,11 @@ def parse():
                     help="FETCH_DB WRITE_DB RUN_LOG [OUT]: summarise two rocprofv3 --pmc runs of "
                          "--headline-only --copy-calibration (FETCH_SIZE, WRITE_SIZE) into OUT (default: the "
                          "FP64 row-pass file under profiles/) and exit (no GPU use)")
-    ap.add_argument("--write-trace", nargs=4, metavar=("DB", "OUT_MD", "TITLE", "COMMAND"), default=None,
-                    help="summarise the timed region of a rocprofv3 --kernel-trace database (the kernels "
-                         "between the trace markers 1 and 2) into a markdown table and exit (no GPU use)")
+    ap.add_argument("--write-trace", nargs="+", metavar="ARG", default=None,
+                    help="DB OUT_MD TITLE COMMAND [REPLAYS]: summarise the timed region of a rocprofv3 "
+                         "--kernel-trace database (the kernels between the trace markers 1 and 2) into a "
+                         "markdown table, with the first execution's timeline when REPLAYS is given, and "
+                         "exit (no GPU use)")
     ap.add_argument("--write-counters", nargs=4, metavar=("DB", "OUT_MD", "TITLE", "COMMAND"), default=None,
                     help="average every counter of a rocprofv3 --pmc database per kernel over the dispatches "
                          "between trace markers 1 and 2 into a markdown table and exit (no GPU use)")
@@ -326,37 +328,70 @@ def time_plan(thx, torch, plan, a, b, steps, warmup, phase=None):
     return (t1 - t0) * 1e3 / steps, plan.timings(reset=True)
 
 
-def write_trace(db, out_md, title, command):
+def busy_union(iv):
+    """Length of the union of [start, end) intervals (time with at least one kernel running)."""
+    tot, cur_s, cur_e = 0, None, None
+    for st, en in sorted(iv):
+        if cur_e is None or st > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+    return tot + (cur_e - cur_s if cur_e is not None else 0)
+
+
+def write_trace(db, out_md, title, command, replays=None):
     """Markdown table of the kernels between the first trace marker 1 and the next marker 2 of a
     rocprofv3 --kernel-trace database (the timed loop only: no plan, tuning or warm-up dispatches),
-    with the loop's span against the sum of its kernel durations (gaps between launches)."""
+    with the loop's span against the sum of its kernel durations and against the time during
+    which at least one kernel runs (concurrent graph branches overlap).  With `replays` (the
+    number of executions in the loop, equal kernel sequences), the first execution's dispatches
+    are listed with their start and end relative to its first dispatch."""
     import sqlite3
     con = sqlite3.connect(db)
-    rows = con.execute("select name, start, end, grid_x from kernels order by start").fetchall()
+    rows = con.execute("select name, start, end, grid_x, grid_y * grid_z, workgroup_x * workgroup_y * workgroup_z "
+                       "from kernels order by start").fetchall()
     con.close()
-    marks = [(i, gx) for i, (n, _, _, gx) in enumerate(rows) if "k_trace_marker" in n]
+    marks = [(i, r[3]) for i, r in enumerate(rows) if "k_trace_marker" in r[0]]
     i0 = next(i for i, gx in marks if gx == 64)
     i1 = next(i for i, gx in marks if gx == 128 and i > i0)
     win = [r for r in rows[i0 + 1:i1] if "k_trace_marker" not in r[0]]
     stats = {}
-    for n, st, en, _ in win:
+    for n, st, en, *_ in win:
         name = n.split("(")[0].replace("void ", "")
         stats.setdefault(name, []).append((en - st) / 1e3)
     total = sum(sum(v) for v in stats.values())
     span = (max(r[2] for r in win) - min(r[1] for r in win)) / 1e3
+    busy = busy_union([(r[1], r[2]) for r in win]) / 1e3
+    rep_arg = f" {int(replays)}" if replays else ""
     lines = [f"# Kernel trace: {title}", "",
              "Command (repo root $R, output directory $OUT, from /tmp with TMPDIR=/tmp), then the summary:", "",
              "```", command,
-             f"python3 $R/bench.py --write-trace <kt_results.db> <this file> \"{title}\" \"<the command>\"",
+             f"python3 $R/bench.py --write-trace <kt_results.db> <this file> \"{title}\" \"<the command>\"{rep_arg}",
              "```", "",
              f"Only the dispatches of the timed loop (between trace markers 1 and 2): {len(win)} launches, "
-             f"{total:.1f} us of kernel time in a span of {span:.1f} us "
-             f"({100 * (span - total) / span:.1f}% of the span outside kernels).", "",
+             f"{total:.1f} us of kernel time in a span of {span:.1f} us; at least one kernel runs during "
+             f"{busy:.1f} us of it ({100 * (span - busy) / span:.1f}% of the span with no kernel running).", "",
              "| kernel | calls | total (us) | average (us) | min (us) | max (us) | % |",
              "|---|---:|---:|---:|---:|---:|---:|"]
     for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{name}` | {len(v)} | {sum(v):.1f} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
                      f"{max(v):.1f} | {100 * sum(v) / total:.1f} |")
+    if replays and len(win) % int(replays) == 0:
+        per = len(win) // int(replays)
+        first = win[:per]
+        t0 = first[0][1]
+        fspan = (max(r[2] for r in first) - t0) / 1e3
+        fbusy = busy_union([(r[1], r[2]) for r in first]) / 1e3
+        lines += ["", f"First of the {int(replays)} executions: {per} dispatches in {fspan:.1f} us, at least one "
+                  f"kernel running during {fbusy:.1f} us ({100 * (fspan - fbusy) / fspan:.1f}% idle).", "",
+                  "| # | kernel | workgroups | start (us) | end (us) | duration (us) |",
+                  "|---:|---|---:|---:|---:|---:|"]
+        for i, (n, st, en, gx, gyz, wg) in enumerate(first):
+            name = n.split("(")[0].replace("void ", "")
+            lines.append(f"| {i} | `{name}` | {gx * gyz // max(1, wg)} | {(st - t0) / 1e3:.1f} | "
+                         f"{(en - t0) / 1e3:.1f} | {(en - st) / 1e3:.1f} |")
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -920,6 +920,37 @@ __device__ __forceinline__ Pair sc_lane(const KindDesc &k, const double *al, int
     return Pair{q <= N ? d2_of(k, q) * al[q] : 0.0, 0.0};
 }
 
+// The same values with one 16-byte load per lane when the vector's first
+// coefficient is 16-byte aligned (a16, uniform per vector) and the lane lies
+// inside the vector (the two 8-byte loads of sc_lane touch every cache line
+// twice).
+__device__ __forceinline__ Pair sc_lane_v(const KindDesc &k, const double *al, int64_t N, int64_t q, bool a16)
+{
+    if (k.parity && a16 && 2 * q + 1 <= N) {
+        const double2 v = *(const double2 *)(al + 2 * q);
+        return Pair{d2_of(k, 2 * q) * v.x, d2_of(k, 2 * q + 1) * v.y};
+    }
+    return sc_lane(k, al, N, q);
+}
+
+// beta at the components of lane q: D1 g times the scanned values, one 16-byte
+// store per lane under the same conditions as sc_lane_v
+__device__ __forceinline__ void sc_store(const KindDesc &k, double *be, int64_t N, int64_t q, double g, double vx,
+                                         double vy, bool a16)
+{
+    if (k.parity) {
+        const int64_t j0 = 2 * q, j1 = 2 * q + 1;
+        if (a16 && j1 <= N) {
+            *(double2 *)(be + j0) = double2{d1_of(k, j0) * g * vx, d1_of(k, j1) * g * vy};
+        } else {
+            if (j0 <= N) be[j0] = d1_of(k, j0) * g * vx;
+            if (j1 <= N) be[j1] = d1_of(k, j1) * g * vy;
+        }
+    } else if (q <= N) {
+        be[q] = d1_of(k, q) * g * vx;
+    }
+}
+
 // Sums in a fixed order (deterministic): within a wave by butterfly shuffles,
 // across the SC_NT / 64 waves through LDS.
 constexpr int SC_NW = SC_NT / 64;
@@ -972,10 +1003,11 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_tot(KindDesc k, VecRef vr, con
     int64_t base, N;
     vec_of(vr, b, ld, N0, base, N);
     const double *al = alpha + base;
+    const bool a16 = ((uintptr_t)al & 15) == 0;
     double x = 0.0, y = 0.0;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
-        const Pair u = sc_lane(k, al, N, (int64_t)c * SC_CH + threadIdx.x + SC_NT * i);
+        const Pair u = sc_lane_v(k, al, N, (int64_t)c * SC_CH + threadIdx.x + SC_NT * i, a16);
         x += u.x;
         y += u.y;
     }
@@ -1004,11 +1036,13 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
     const int64_t nl = k.parity ? N / 2 + 1 : N + 1; // lanes of this vector
     if ((int64_t)c * SC_CH >= nl) return;            // uniform over the block
     const double *al = alpha + base;
+    double *be = beta + base;
+    const bool a16 = (((uintptr_t)al | (uintptr_t)be) & 15) == 0;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t q0 = (int64_t)c * SC_CH;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
-        const Pair u = sc_lane(k, al, N, q0 + t + SC_NT * i);
+        const Pair u = sc_lane_v(k, al, N, q0 + t + SC_NT * i, a16);
         lx[sc_pad(t + SC_NT * i)] = u.x;
         ly[sc_pad(t + SC_NT * i)] = u.y;
     }
@@ -1052,18 +1086,10 @@ __global__ __launch_bounds__(SC_NT) void k_suffix_apply(KindDesc k, VecRef vr, c
     }
     __syncthreads();
     const double g = tsym[0] * hk[0];
-    double *be = beta + base;
 #pragma unroll
     for (int i = 0; i < SC_PER; ++i) {
         const int li = t + SC_NT * i;
-        const int64_t q = q0 + li;
-        if (k.parity) {
-            const int64_t j0 = 2 * q, j1 = 2 * q + 1;
-            if (j0 <= N) be[j0] = d1_of(k, j0) * g * lx[sc_pad(li)];
-            if (j1 <= N) be[j1] = d1_of(k, j1) * g * ly[sc_pad(li)];
-        } else if (q <= N) {
-            be[q] = d1_of(k, q) * g * lx[sc_pad(li)];
-        }
+        sc_store(k, be, N, q0 + li, g, lx[sc_pad(li)], ly[sc_pad(li)], a16);
     }
 }
 
@@ -1095,21 +1121,14 @@ __global__ __launch_bounds__(SS_NT) void k_suffix_small(KindDesc k, VecRef vr, c
     const int R = (int)((nl + 63) / 64);
     const double *al = alpha + base;
     double *be = beta + base;
+    const bool a16 = (((uintptr_t)al | (uintptr_t)be) & 15) == 0;
     const double g = tsym[0] * hk[0];
     double cx = 0.0, cy = 0.0;
-    Pair u = sc_lane(k, al, N, (int64_t)(R - 1) * 64 + t);
+    Pair u = sc_lane_v(k, al, N, (int64_t)(R - 1) * 64 + t, a16);
     for (int i = R - 1; i >= 0; --i) {
-        const Pair nxt = i > 0 ? sc_lane(k, al, N, (int64_t)(i - 1) * 64 + t) : Pair{0.0, 0.0};
+        const Pair nxt = i > 0 ? sc_lane_v(k, al, N, (int64_t)(i - 1) * 64 + t, a16) : Pair{0.0, 0.0};
         const double sx = wave_suffix(u.x), sy = wave_suffix(u.y);
-        const double vx = sx + cx, vy = sy + cy;
-        const int64_t q = (int64_t)i * 64 + t;
-        if (k.parity) {
-            const int64_t j0 = 2 * q, j1 = 2 * q + 1;
-            if (j0 <= N) be[j0] = d1_of(k, j0) * g * vx;
-            if (j1 <= N) be[j1] = d1_of(k, j1) * g * vy;
-        } else if (q <= N) {
-            be[q] = d1_of(k, q) * g * vx;
-        }
+        sc_store(k, be, N, (int64_t)i * 64 + t, g, sx + cx, sy + cy, a16);
         cx += __shfl(sx, 0, 64);
         cy += __shfl(sy, 0, 64);
         u = nxt;

@@ -1688,8 +1688,10 @@ struct thx_batch {
     hipStream_t cap_stream = nullptr;
     // Buckets read and write disjoint coefficients, so the FFT buckets run in two
     // lanes: one bucket's launch ramps and short single-workgroup transforms
-    // overlap another's HBM-bound passes (the dense product and the unit step stay
-    // in the first lane: overlapped with each other they measured slower).  The
+    // overlap another's HBM-bound passes (the dense product and the unit steps stay
+    // in the first lane: overlapped with each other they measured slower, e.g.
+    // 0.183 against 0.170 ms for the unit steps of 65536 vectors of degree 255
+    // beside 64 of degree 2^18).  The
     // side lane forks from and joins the calling stream through events, also under
     // capture (the graph then has two branches).
     hipStream_t side_stream = nullptr;

@@ -457,6 +457,54 @@ def test_unit_step_short_vectors_large_batch(thx):
                    entry_scale=2 * n + 1, label=f"member {i} n={n} ")
 
 
+# long vectors (two-pass scan) and short ones (one wave per vector) with 16-byte
+# accesses where a vector starts on a 16-byte boundary and 8-byte ones elsewhere:
+# N + 1 odd makes every other strided vector start at an odd index, and CSR
+# members after an even degree do too; vectors of one chunk, of more chunks than
+# a workgroup has threads (2^20 parity: 257), ragged ends; a second execution
+# gives the same bits
+@pytest.mark.parametrize("kind,params", [(2, (1.5, 0.5)), (4, (1.5, 0.5))])
+def test_unit_step_alignment_and_chunks(thx, kind, params):
+    import torch
+    N, batch = 300000, 3
+    alpha = inputs.coeffs(N, 1.0, seed=91, batch=batch)
+    degrees = np.array([5000, 2049, 300001, 70000, 4095, 4096, 1 << 20, 2, 0, 1025, 254, 255], dtype=np.int64)
+    flat, parts = _batch_inputs(degrees, 1.0, 93)
+    print(f"[case] unit step kind={kind} N={N} batch={batch} degrees={degrees.tolist()}", flush=True)
+    plan = thx.Plan(kind, N, EPS64, thx.FP64, params=params)
+    assert plan.path == 4
+    bt = thx.Batch(kind, degrees, EPS64, thx.FP64, params=params)
+    a, fa = _dev(alpha), _dev(flat)
+    outs = []
+    for _ in range(2):
+        b = torch.full_like(a, float("nan"))
+        plan.execute(a, b)
+        fb = torch.full_like(fa, float("nan"))
+        bt.execute(fa, fb)
+        torch.cuda.synchronize()
+        outs.append((b.cpu().numpy(), fb.cpu().numpy()))
+    (b0, f0), (b1, f1) = outs
+    assert np.array_equal(b0, b1) and np.array_equal(f0, f1)
+    name = ORACLE_KIND[kind]
+    # max |A_jk|: 2n + 1 for ultraspherical 3/2 -> 1/2; 1 for Laguerre 3/2 -> 1/2 (every entry on and
+    # above the diagonal is 1: the generalised Laguerre polynomials are partial sums of those one
+    # parameter lower)
+    scale = (lambda n: 2 * n + 1) if kind == 2 else (lambda n: 1.0)
+    rows = inputs.sample_rows(N, 64, seed=5)
+    for i in range(batch):
+        ref = oracle.matvec(name, alpha[i], params, rows=rows)
+        bars.check(b0[i][rows], ref, alpha[i], TOL64, kind, params, rows=rows, entry_scale=scale(N),
+                   label=f"strided {i} ")
+    for i, n in enumerate(degrees.tolist()):
+        al = parts[i]
+        o = int(bt.offsets[i])
+        r = None if n <= 5000 else inputs.sample_rows(n, 64, seed=i)
+        ref = oracle.matvec(name, al, params, rows=r)
+        got = f0[o:o + n + 1]
+        bars.check(got if r is None else got[r], ref, al, TOL64, kind, params, rows=r, entry_scale=scale(n),
+                   label=f"member {i} n={n} ")
+
+
 def test_unit_step_full_size_sampled(thx):
     N = 1 << 20
     plan, alpha, got = _run(thx, thx.ULTRA2ULTRA, N, thx.FP64, params=(1.5, 0.5), seed=5)
