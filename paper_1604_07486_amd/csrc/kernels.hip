@@ -1177,7 +1177,7 @@ static_assert(DENSE_PAD % DN_BK == 0, "dense tiling");
 // 16 vectors, each taking every other output tile, so both keep the same
 // triangular share).
 template <int BN, int BM = 64>
-__global__ __launch_bounds__(DN_NT) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
+__global__ __launch_bounds__(DN_NT) __attribute__((amdgpu_waves_per_eu(BM == 32 ? 3 : 2))) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
                                                  const double *__restrict__ alpha, int64_t ld,
                                                  double *__restrict__ beta, int64_t N0, int64_t batch)
 {
@@ -1355,7 +1355,7 @@ __global__ void k_split_matrix(const double *__restrict__ At, int npad, v4u *__r
 // of its own 16 vectors straight into operand registers (also one chunk ahead),
 // splits them, and runs 8 products per output tile of the chunk.
 template <int JB>
-__global__ __launch_bounds__(DB_NT) void k_dense_bf16(const v4u *__restrict__ Bp, int npad, VecRef vr,
+__global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256 ? 2 : 4))) void k_dense_bf16(const v4u *__restrict__ Bp, int npad, VecRef vr,
                                                       const double *__restrict__ alpha, int64_t ld,
                                                       double *__restrict__ beta, int64_t N0, int64_t batch)
 {
