@@ -1732,8 +1732,10 @@ MultiPassGeom multipass_geom(int64_t L, int64_t row)
 {
     MultiPassGeom g;
     g.L = L;
-    const bool ok = (row == mp_row_short<T>() || row == mp_row_long<T>()) && L % row == 0 &&
-                    column_length_ok(L / row);
+    const bool xl = mp_row_xl<T>() > 0 && row == mp_row_xl<T>() && L % row == 0 &&
+                    (L / row == 256 || L / row == 512);
+    const bool ok = xl || ((row == mp_row_short<T>() || row == mp_row_long<T>()) && L % row == 0 &&
+                           column_length_ok(L / row));
     if (!ok) row = L / mp_row_short<T>() <= 512 ? mp_row_short<T>() : mp_row_long<T>();
     g.L1 = row;
     g.L2 = L / g.L1;
@@ -2102,6 +2104,14 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
     if (amid < n) Wg[amid] = accm;
 }
 
+// Column lengths built for a row length: L1 L2 <= MP_LMAX, and for the
+// double-precision rows of 8192 points only columns of 256 and 512
+template <typename T, int L1, int L2>
+constexpr bool mp_cols_built()
+{
+    return (int64_t)L1 * L2 <= MP_LMAX && (L1 != mp_row_xl<T>() || L2 == 256 || L2 == 512);
+}
+
 // Column lengths instantiated for each row length (L1 L2 <= MP_LMAX).
 #define THX_L2_CASES(X) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) \
     X(10) X(20) X(40) X(80) X(160) X(320) X(640) \
@@ -2116,7 +2126,7 @@ bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, cons
     switch (g.L2) {
 #define THX_P1(LL2)                                                                                       \
     case LL2:                                                                                             \
-        if constexpr ((int64_t)L1 * LL2 <= MP_LMAX) {                                                     \
+        if constexpr (mp_cols_built<T, L1, LL2>()) {                                                     \
             const dim3 grid((unsigned)(L1 / mp_tc<T, LL2>() * nsg * batch));                               \
             if (spb > 1)                                                                                  \
                 k_mp_p1<T, L1, LL2, true><<<grid, mp_nt<T, LL2>(), 0, s>>>(                               \
@@ -2149,6 +2159,10 @@ bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, 
     if (g.L1 == mp_row_long<T>())
         return mp_p1_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
                                                    twA, s);
+    if constexpr (mp_row_xl<T>() > 0)
+        if (g.L1 == mp_row_xl<T>())
+            return mp_p1_l2<T, (int)mp_row_xl<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
+                                                     twA, s);
     return false;
 }
 template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
@@ -2175,7 +2189,10 @@ bool launch_mp_p2(const MultiPassGeom &g, void *U, int nslots, int64_t batch, co
         mp_p2_run<T, (int)mp_row_short<T>()>(g, U, nslots, batch, that_perm, twL1, twA, twL2, full, out, scale, s);
     else if (g.L1 == mp_row_long<T>())
         mp_p2_run<T, (int)mp_row_long<T>()>(g, U, nslots, batch, that_perm, twL1, twA, twL2, full, out, scale, s);
-    else
+    else if constexpr (mp_row_xl<T>() > 0) {
+        if (g.L1 != mp_row_xl<T>() || (g.L2 != 256 && g.L2 != 512)) return false;
+        mp_p2_run<T, (int)mp_row_xl<T>()>(g, U, nslots, batch, that_perm, twL1, twA, twL2, full, out, scale, s);
+    } else
         return false;
     return true;
 }
@@ -2227,7 +2244,7 @@ bool mp_p3_l2(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, cons
     switch (g.L2) {
 #define THX_P3(LL2)                                                                                   \
     case LL2:                                                                                         \
-        if constexpr ((int64_t)L1 * LL2 <= MP_LMAX) {                                                 \
+        if constexpr (mp_cols_built<T, L1, LL2>()) {                                                 \
             k_mp_p3<T, L1, LL2><<<dim3((unsigned)(L1 / mp_tc<T, LL2>()), (unsigned)G, (unsigned)batch), \
                                   mp_nt<T, LL2>(), 0, s>>>((const cpx<T> *)U, nc, n,                  \
                                                            (const cpx<T> *)ell, slot0, nslots, spg,   \
@@ -2253,6 +2270,10 @@ bool launch_mp_p3(const MultiPassGeom &g, const void *U, int64_t nc, int64_t n, 
         return mp_p3_l2<T, (int)mp_row_short<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch, twL2, s);
     if (g.L1 == mp_row_long<T>())
         return mp_p3_l2<T, (int)mp_row_long<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch, twL2, s);
+    if constexpr (mp_row_xl<T>() > 0)
+        if (g.L1 == mp_row_xl<T>())
+            return mp_p3_l2<T, (int)mp_row_xl<T>()>(g, U, nc, n, ell, slot0, nslots, spg, G, Wpart, gofs, batch,
+                                                     twL2, s);
     return false;
 }
 template bool launch_mp_p3<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, int, void *, int, int64_t, const void *, hipStream_t);

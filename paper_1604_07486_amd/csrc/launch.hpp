@@ -194,6 +194,10 @@ template <typename T> constexpr int64_t lds_max_len() { return sizeof(T) == 8 ? 
 // 128-byte segments.  Longest transform: MP_LMAX.
 template <typename T> constexpr int64_t mp_row_short() { return sizeof(T) == 8 ? 2048 : 4096; }
 template <typename T> constexpr int64_t mp_row_long() { return sizeof(T) == 8 ? 4096 : 8192; }
+// double precision only: rows of 8192 points (one 512-thread workgroup per CU)
+// with columns of 256 or 512, so that L = 2^21 and 2^22 keep the 16-column tiles
+// of columns of 512 instead of 8-column tiles of columns of 1024
+template <typename T> constexpr int64_t mp_row_xl() { return sizeof(T) == 8 ? 8192 : 0; }
 constexpr int64_t MP_LMAX = (int64_t)1 << 22;
 
 // single-workgroup path: W[g] = sum_{s in group g} ell_s o IFFT(FFT(ell_s o X) . that),

@@ -1466,14 +1466,15 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
         p->lds_radix = best_r;
     } else if (p->path == 2) {
         const bool f64 = p->prec == THX_FP64;
-        const int64_t rows[2] = {f64 ? mp_row_short<double>() : mp_row_short<float>(),
-                                 f64 ? mp_row_long<double>() : mp_row_long<float>()};
+        const int64_t rows[3] = {f64 ? mp_row_short<double>() : mp_row_short<float>(),
+                                 f64 ? mp_row_long<double>() : mp_row_long<float>(),
+                                 f64 ? mp_row_xl<double>() : mp_row_xl<float>()};
         int64_t best_row = p->geom.L1;
         int best_p3 = p->p3_blocks;
         float tb = 1e30f;
         bool best_fuse = false;
         for (int64_t row : rows) {
-            if (p->L / row < 2 || p->L / row > 1024) continue;
+            if (row <= 0 || p->L / row < 2 || p->L / row > 1024) continue;
             configure_rows(p, row, s);
             if (p->geom.L1 != row) continue;
             p->p1_blocks = 0;

@@ -159,6 +159,23 @@ def test_leg2cheb_row_lengths(thx, N, prec, row, monkeypatch):
     assert plan.path == 2
 
 
+# double-precision rows of 8192 points (columns of 256 at L = 2^21, 512 at
+# L = 2^22), sampled rows against the oracle, several vectors, slot groups in the
+# forward column pass
+@pytest.mark.parametrize("N,batch,p1", [((1 << 21) - 3, 2, 0), (1 << 21, 1, 100), ((1 << 22) - 1, 1, 0)])
+def test_leg2cheb_rows_8192_fp64(thx, N, batch, p1, monkeypatch):
+    monkeypatch.setenv("THX_ROW_LEN", "8192")
+    monkeypatch.setenv("THX_P1_BLOCKS", str(p1))
+    plan, alpha, got = _run(thx, thx.LEG2CHEB, N, thx.FP64, flags=thx.FLAG_FORCE_FFT, seed=N + p1, batch=batch)
+    L1, L2, _ = plan.fft_geometry()
+    assert plan.path == 2 and L1 == 8192 and L2 in (256, 512), plan.fft_geometry()
+    for i in range(batch):
+        rows = inputs.sample_rows(N, 256, seed=i + 7)
+        ref = oracle.matvec("leg2cheb", alpha[i], rows=rows)
+        print(f"  vector {i}: K={plan.rank} L={plan.fft_length} geometry={plan.fft_geometry()}", flush=True)
+        bars.check(got[i][rows], ref, alpha[i], TOL64, 0, rows=rows, label=f"vector {i} ")
+
+
 # both FFT radices of the single-workgroup path (THX_LDS_RADIX is read at plan
 # creation; the autotuner chooses between them), every transform length
 @pytest.mark.parametrize("radix", [8, 16])
