@@ -429,7 +429,8 @@ def lds_flops(S, L, nc, batch=1):
 
 def run_config1(thx, torch, inputs, oracle, dev, steps):
     """Legendre -> Chebyshev, one vector of degree 2048, FP64, Hankel tol 1e-15: one launch of the
-    single-workgroup FFT path per conversion; its rate against the FP64 vector peak."""
+    single-workgroup FFT path per conversion; its rate against the FP64 vector peak.  Timed as plan
+    executions (one call each) and as replays of a one-member batch graph."""
     N = 2048
     alpha = inputs.coeffs(N, 1.0, seed=2048)
     a = torch.from_numpy(alpha).to(dev)
@@ -437,8 +438,26 @@ def run_config1(thx, torch, inputs, oracle, dev, steps):
     plan = thx.Plan(thx.LEG2CHEB, N, 1e-15, thx.FP64, flags=thx.FLAG_FORCE_FFT)
     plan.autotune(1)
     reps = max(200, steps * 10)
-    ms, tim = time_plan(thx, torch, plan, a, b, reps, 20, phase="toep_lds")
-    err = float(np.max(np.abs(b.cpu().numpy() - oracle.matvec("leg2cheb", alpha))) / np.sum(np.abs(alpha)))
+    ms, _ = time_plan(thx, torch, plan, a, b, reps, 20)
+    ref = oracle.matvec("leg2cheb", alpha)
+    err = float(np.max(np.abs(b.cpu().numpy() - ref)) / np.sum(np.abs(alpha)))
+    _, tim = time_plan(thx, torch, plan, a, b, reps, 5, phase="toep_lds")
+    # the same conversion as a one-member batch replayed as a hipGraph (no launch gaps between
+    # its kernels)
+    bt = thx.Batch(thx.LEG2CHEB, np.array([N], dtype=np.int64), 1e-15, thx.FP64,
+                   flags=thx.FLAG_FORCE_FFT | thx.FLAG_AUTOTUNE)
+    bb = torch.empty_like(a)
+    for _ in range(20):
+        bt.execute(a, bb, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt.execute(a, bb, graph=True)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3 / reps
+    gerr = float(np.max(np.abs(bb.cpu().numpy() - ref)) / np.sum(np.abs(alpha)))
+    gbk = bt.buckets()
+    del bt
     tot, cnt = tim["toep_lds"]
     kms = tot / cnt
     fl = lds_flops(plan.rank, plan.fft_length, N // 2 + 1)
@@ -447,6 +466,8 @@ def run_config1(thx, torch, inputs, oracle, dev, steps):
                         "Hankel tol 1e-15, FFT path (length 2048 complex per parity half), plan autotuned",
             "ms_per_conversion": round(ms, 5), "coeffs_per_s": round((N + 1) / (ms * 1e-3), 1),
             "K": plan.rank, "L": plan.fft_length, "lds_radix": plan.lds_radix, "max_err_over_l1": err,
+            "graph_replay": {"ms_per_conversion": round(gms, 5), "coeffs_per_s": round((N + 1) / (gms * 1e-3), 1),
+                             "max_err_over_l1": gerr, "buckets": gbk},
             "roofline": {"kernel": "toep_lds", "bound": "alu", "achieved": round(tf, 3),
                          "peak": VALU_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / VALU_FP64_TFLOPS, 5),
                          "flops_per_launch": int(fl), "avg_launch_ms": round(kms, 5), "launches": cnt}}

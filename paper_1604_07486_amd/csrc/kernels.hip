@@ -646,6 +646,18 @@ __global__ __launch_bounds__(256) void k_unpack(KindDesc k, VecRef vr, const dou
     const int64_t gstride = batch * nc;
     double wx = 0.0, wy = 0.0, wsum = 0.0;
     int g = 0;
+    // eight partial groups in flight per round (the sum keeps the group order)
+    for (; g + 8 <= G; g += 8) {
+        cpx<T> v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Wa[(int64_t)(g + u) * gstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            wx += (double)v[u].x;
+            wy += (double)v[u].y;
+            wsum += (double)v[u].x + (double)v[u].y;
+        }
+    }
     for (; g + 4 <= G; g += 4) {
         cpx<T> v[4];
 #pragma unroll
