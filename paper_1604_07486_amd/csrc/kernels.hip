@@ -1384,9 +1384,12 @@ __global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256
     int64_t abase, an;
     if (b0 + 16 * w + m < batch) vec_of(vr, b0 + 16 * w + m, ld, N0, abase, an);
     else abase = 0, an = -1;
-    double xr[8];
+    // alpha runs two chunks ahead (two register sets, the loop unrolled by two so
+    // that each set keeps its registers), the matrix parts one chunk ahead: with two
+    // workgroups per CU that keeps about 64 KiB of alpha reads in flight per CU
+    double xa[8], xb[8];
     v4u br[BL];
-    auto fetch = [&](int kc) {
+    auto fetch_alpha = [&](int kc, double *xr) {
         const int64_t k0 = (int64_t)DB_KC * kc + 8 * g;
         if (k0 + 7 <= an && ((abase + k0) & 1) == 0) {
             // the lane's eight values inside the vector and 16-byte aligned: four 16-byte loads
@@ -1401,20 +1404,26 @@ __global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256
 #pragma unroll
             for (int i = 0; i < 8; ++i) xr[i] = k0 + i <= an ? alpha[abase + k0 + i] : 0.0;
         }
+    };
+    // columns from DB_KC (kc + 1) on are zero in chunk kc (At[k][j] = 0 for k < j) and
+    // their tiles are skipped, so they are neither read nor staged
+    auto fetch_matrix = [&](int kc) {
+        const int jlim = min(jn, DB_KC * (kc + 1) - j0);
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
             const int u = (int)threadIdx.x + DB_NT * e; // (part, column, k group)
             const int p = u / (JB * 4), r = u % (JB * 4);
-            br[e] = (r >> 2) < jn ? Bp[((int64_t)(kc * 3 + p) * npad + j0) * 4 + r] : v4u{0, 0, 0, 0};
+            br[e] = (r >> 2) < jlim ? Bp[((int64_t)(kc * 3 + p) * npad + j0) * 4 + r] : v4u{0, 0, 0, 0};
         }
     };
     v4f acc[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) acc[t] = v4f{0, 0, 0, 0};
     const int nkc = npad / DB_KC;
-    // chunks of k below the first output are zero (At[k][j] = 0 for k < j)
-    fetch(j0 / DB_KC);
-    for (int kc = j0 / DB_KC; kc < nkc; ++kc) {
+    // one chunk: stage the matrix parts, split the chunk's alpha (xr) into bfloat16
+    // parts, refill xr with the chunk two ahead, and accumulate every tile the
+    // chunk reaches
+    auto chunk = [&](int kc, double *xr) {
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < BL; ++e) bs[threadIdx.x + DB_NT * e] = br[e];
@@ -1422,7 +1431,8 @@ __global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256
 #pragma unroll
         for (int i = 0; i < 8; ++i) f[i] = (float)xr[i];
         __syncthreads();
-        if (kc + 1 < nkc) fetch(kc + 1);
+        if (kc + 1 < nkc) fetch_matrix(kc + 1);
+        if (kc + 2 < nkc) fetch_alpha(kc + 2, xr);
         v4u xh, xm, xl;
         split_bf16x3(f, xh, xm, xl);
         const v8bf ah = __builtin_bit_cast(v8bf, xh), am = __builtin_bit_cast(v8bf, xm),
@@ -1445,6 +1455,15 @@ __global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256
             c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, c, 0, 0, 0);
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
         }
+    };
+    // chunks of k below the first output are zero (At[k][j] = 0 for k < j)
+    const int kc0 = j0 / DB_KC;
+    fetch_alpha(kc0, xa);
+    fetch_matrix(kc0);
+    if (kc0 + 1 < nkc) fetch_alpha(kc0 + 1, xb);
+    for (int kc = kc0; kc < nkc; kc += 2) {
+        chunk(kc, xa);
+        if (kc + 1 < nkc) chunk(kc + 1, xb);
     }
     int64_t sbase[4], sn[4];
 #pragma unroll
