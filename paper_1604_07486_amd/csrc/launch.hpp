@@ -155,10 +155,16 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_identity(double *I, int64_t n, int64_t ld, hipStream_t s);
 
 // ---- unit steps: beta = D1 t_0 h_0 (suffix sums of D2 alpha) ----------------------
-// tot: [batch][suffix_chunks][2] doubles of workspace (unused for short vectors:
+// tot: suffix_tot_doubles(k, N, batch) doubles of workspace, the totals of the
+// SCAN_SPLIT sub-chunks of every chunk (unused for short vectors:
 // at most SS_LANES lanes run one wave per vector in one launch, any batch size)
 constexpr int SS_LANES = 1024;
+constexpr int SCAN_SPLIT = 2;
 int suffix_chunks(const KindDesc &k, int64_t N);
+inline int64_t suffix_tot_doubles(const KindDesc &k, int64_t N, int64_t batch)
+{
+    return 2 * SCAN_SPLIT * batch * suffix_chunks(k, N);
+}
 bool suffix_small(const KindDesc &k, int64_t N);
 void launch_suffix(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha, int64_t ld,
                    double *beta, int64_t N, int64_t batch, const double *tsym, const double *hk, double *tot,

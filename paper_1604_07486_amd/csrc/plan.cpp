@@ -194,7 +194,7 @@ struct thx_plan {
     void *X = nullptr, *Wp = nullptr, *U = nullptr;
     double *row0 = nullptr;
     double *row0_part = nullptr; // [batch][ROW0_PMAX] partial sums of row 0
-    double *sfx_tot = nullptr;   // path 4: [batch][chunks][2] chunk totals
+    double *sfx_tot = nullptr;   // path 4: sub-chunk totals (suffix_tot_doubles)
     int64_t U_slots = 0;
     int Gmax = 0;
     int64_t *vl_off = nullptr, *vl_deg = nullptr; // variable-length executions: per-member offsets, degrees
@@ -1026,7 +1026,7 @@ void ensure_workspace(thx_plan *p, int64_t batch)
         dfree(p->sfx_tot);
         p->sfx_tot = nullptr;
         p->ws_batch = 0;
-        p->sfx_tot = dalloc<double>(2 * batch * suffix_chunks(p->kd, p->N));
+        p->sfx_tot = dalloc<double>(suffix_tot_doubles(p->kd, p->N, batch));
         p->ws_batch = batch;
         return;
     }
@@ -1224,7 +1224,7 @@ int64_t carve_stage(const thx_plan *p, int64_t batch, int64_t chunk, char *regio
     };
     Ws a, b;
     if (p->path == 4) {
-        a.sfx_tot = (double *)take(16 * batch * suffix_chunks(p->kd, p->N));
+        a.sfx_tot = (double *)take(8 * suffix_tot_doubles(p->kd, p->N, batch));
     } else if (p->path == 1 || p->path == 2) {
         auto one = [&](const thx_plan *q, Ws &x) {
             const int64_t es = (int64_t)q->esize();
