@@ -456,6 +456,25 @@ __global__ void k_pack(KindDesc k, VecRef vr, const double *alpha, int64_t ld, i
     X[b * nc + a] = cpx<T>{(T)x, (T)y};
 }
 
+// lane a of a vector (base pointer al, degree N) as k_pack forms it, in precision T
+template <typename T>
+__device__ __forceinline__ cpx<T> x_lane(const KindDesc &k, const double *al, int64_t N, int64_t a)
+{
+    double x = 0.0, y = 0.0;
+    if (k.parity && 2 * a + 1 <= N && ((uintptr_t)(al + 2 * a) & 15) == 0) {
+        const double2 v = *(const double2 *)(al + 2 * a); // both inside the vector: one 16-byte load
+        x = d2_of(k, 2 * a) * v.x;
+        y = d2_of(k, 2 * a + 1) * v.y;
+    } else if (k.parity) {
+        const int64_t j0 = 2 * a, j1 = 2 * a + 1;
+        if (j0 <= N) x = d2_of(k, j0) * al[j0];
+        if (j1 <= N) y = d2_of(k, j1) * al[j1];
+    } else if (a <= N) {
+        x = y = d2_of(k, a) * al[a];
+    }
+    return cpx<T>{(T)x, (T)y};
+}
+
 template <typename T>
 void launch_pack(const KindDesc &k, const int64_t *off, const int64_t *deg, const double *alpha,
                  int64_t ld, int64_t N, int64_t batch, void *X, int64_t nc, hipStream_t s)
@@ -1801,7 +1820,7 @@ template <typename T, int L1, int L2, bool SG>
 __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int slot0,
     int nslots, int spb, const cpx<T> *__restrict__ src, cpx<T> *__restrict__ U, int64_t batch,
-    const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA)
+    const cpx<T> *__restrict__ twL2, const cpx<T> *__restrict__ twA, AlphaIn ain)
 {
     constexpr int TC = mp_tc<T, L2>();
     constexpr int NT = mp_nt<T, L2>();
@@ -1816,6 +1835,14 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const int sg = (int)((blockIdx.x / tiles) % nsg);
     const int64_t b = blockIdx.x / (tiles * nsg);
     const cpx<T> *Xb = X ? X + b * nc : nullptr;
+    // lanes formed from the vector itself when no packed X is given (one slot per
+    // workgroup only: the slot-group form reads X, its registers are taken)
+    int64_t abase = 0, aN = -1;
+    if (!SG && ain.alpha) vec_of(VecRef{ain.off, ain.deg}, b, ain.ld, ain.N0, abase, aN);
+    auto xin = [&](int64_t a) -> cpx<T> {
+        if constexpr (SG) return Xb[a];
+        else return ain.alpha ? x_lane<T>(ain.k, ain.alpha + abase, aN, a) : Xb[a];
+    };
     // slots e with e mod RF > RF/2 hold positions above L/2: zero padding
     auto live = [&](int e, int64_t a) { return e % RF <= RF / 2 && a < n; };
     auto transform_store = [&](cpx<T> *v, int sl) {
@@ -1856,7 +1883,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
             int a2, c;
             F::in_pos(e, a2, c);
             const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-            if (es) v[e] = live(e, a) ? cdiag(es[a], Xb[a]) : cpx<T>{0, 0};
+            if (es) v[e] = live(e, a) ? cdiag(es[a], xin(a)) : cpx<T>{0, 0};
             else v[e] = src[a];
         }
         transform_store(v, sl);
@@ -1868,7 +1895,7 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
             int a2, c;
             F::in_pos(e, a2, c);
             const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-            xv[e] = live(e, a) ? Xb[a] : cpx<T>{0, 0};
+            xv[e] = live(e, a) ? xin(a) : cpx<T>{0, 0};
         }
         for (int sl = s0; sl < s1; ++sl) {
             const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
@@ -2159,7 +2186,7 @@ constexpr bool mp_cols_built()
 template <typename T, int L1>
 bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell, int slot0,
               int nslots, int spb, const void *src, void *U, int64_t batch, const void *twL2, const void *twA,
-              hipStream_t s)
+              hipStream_t s, const AlphaIn &ain)
 {
     const int nsg = (nslots + spb - 1) / spb;
     switch (g.L2) {
@@ -2170,11 +2197,13 @@ bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, cons
             if (spb > 1)                                                                                  \
                 k_mp_p1<T, L1, LL2, true><<<grid, mp_nt<T, LL2>(), 0, s>>>(                               \
                     (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, slot0, nslots, spb,                    \
-                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA);  \
+                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA,   \
+                    ain);                                                                                 \
             else                                                                                          \
                 k_mp_p1<T, L1, LL2, false><<<grid, mp_nt<T, LL2>(), 0, s>>>(                              \
                     (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, slot0, nslots, 1,                      \
-                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA);  \
+                    (const cpx<T> *)src, (cpx<T> *)U, batch, (const cpx<T> *)twL2, (const cpx<T> *)twA,   \
+                    ain);                                                                                 \
             return true;                                                                                  \
         } else {                                                                                          \
             return false;                                                                                 \
@@ -2188,24 +2217,27 @@ bool mp_p1_l2(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, cons
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
                   int slot0, int nslots, int spb, const void *src, void *U, int64_t batch, const void *twL2,
-                  const void *twA, hipStream_t s)
+                  const void *twA, hipStream_t s, const AlphaIn *ainp)
 {
     if (ell && (n > g.L1 * g.L2 / 2 + 1 || n > nc)) return false; // zero padding above L/2 is assumed
     if (spb < 1 || nslots < 1 || (spb > 1 && !ell)) return false;
+    if (ell && !X && (spb > 1 || !(ainp && ainp->alpha))) return false; // slot groups read a packed X
+    AlphaIn ain{};
+    if (ainp && ell) ain = *ainp;
     if (g.L1 == mp_row_short<T>())
         return mp_p1_l2<T, (int)mp_row_short<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
-                                                    twA, s);
+                                                    twA, s, ain);
     if (g.L1 == mp_row_long<T>())
         return mp_p1_l2<T, (int)mp_row_long<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
-                                                   twA, s);
+                                                   twA, s, ain);
     if constexpr (mp_row_xl<T>() > 0)
         if (g.L1 == mp_row_xl<T>())
             return mp_p1_l2<T, (int)mp_row_xl<T>()>(g, X, nc, n, ell, slot0, nslots, spb, src, U, batch, twL2,
-                                                     twA, s);
+                                                     twA, s, ain);
     return false;
 }
-template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
-template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t);
+template bool launch_mp_p1<double>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t, const AlphaIn *);
+template bool launch_mp_p1<float>(const MultiPassGeom &, const void *, int64_t, int64_t, const void *, int, int, int, const void *, void *, int64_t, const void *, const void *, hipStream_t, const AlphaIn *);
 
 template <typename T, int L1>
 void mp_p2_run(const MultiPassGeom &g, void *U, int nslots, int64_t batch, const void *that_perm,

@@ -225,12 +225,22 @@ struct MultiPassGeom {
 template <typename T> MultiPassGeom multipass_geom(int64_t L, int64_t row = 0);
 // true when the three-pass kernels are built for rows of L1 points and columns of L / L1
 bool multipass_ok(int64_t L, int64_t L1);
+// The vectors of an execution in place of a packed X: lane a of vector b is
+// (D2 alpha) at indices 2a, 2a+1 (parity kinds) or (D2 alpha)_a twice, as the
+// pack step would form it; off / deg and ld / N0 as for launch_pack.
+struct AlphaIn {
+    KindDesc k;
+    const int64_t *off, *deg;
+    const double *alpha;
+    int64_t ld, N0;
+};
 // P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr),
-// `spb` consecutive slots per workgroup
+// `spb` consecutive slots per workgroup; with `ain` the lanes of X are formed from
+// the vectors themselves (X unused, no pack step)
 template <typename T>
 bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, const void *ell,
                   int slot0, int nslots, int spb, const void *src, void *U, int64_t batch,
-                  const void *twL2, const void *twA, hipStream_t s);
+                  const void *twL2, const void *twA, hipStream_t s, const AlphaIn *ain = nullptr);
 // P2: row FFT, times permuted symbol, inverse row FFT, conjugate twiddle (full);
 // or forward row FFT only, scaled, written to `out` (symbol transform)
 template <typename T>

@@ -1077,7 +1077,20 @@ int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const 
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
-    {
+    // For one vector up to L = 2^17 the separate forward column pass, one slot
+    // per workgroup, forms its input lanes from the vector itself: one launch
+    // fewer (measured 2 us faster at N = 2^16 in both precisions).  Otherwise the
+    // lanes are packed first: at 2^20 re-forming them for each of 45 slots cost
+    // 8 us more than the pack launch, and on the 4096-polynomial batch 1.2-1.6 ms
+    // more (members at odd offsets take two 8-byte loads per lane in every slot).
+    // The single-workgroup path, the fused row pass and the forward pass with
+    // slot groups (which keeps its tile's lanes in registers across the slots)
+    // always read them packed.
+    const bool packed = !(p->path == 2 && !(p->fuse_p1 && p->geom.L2 <= 4) && p->p1_blocks <= 0 &&
+                          p->L <= ((int64_t)1 << 17) && batch == 1) ||
+                        p->S <= 0;
+    const AlphaIn ain{p->kd, off, deg, alpha, ld, N};
+    if (packed) {
         PhaseTimer t(tm, THX_PHASE_PACK, s);
         launch_pack<T>(p->kd, off, deg, alpha, ld, N, batch, w.X, p->ncs, s);
     }
@@ -1104,8 +1117,9 @@ int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const 
                 } else {
                     {
                         PhaseTimer t(tm, THX_PHASE_COL_FWD, s);
-                        if (!launch_mp_p1<T>(g, w.X, p->ncs, n, ell, s0, ns, p1_slots_per_block(p, ns, batch),
-                                             nullptr, w.U, batch, p->twL2, p->twA, s))
+                        if (!launch_mp_p1<T>(g, packed ? w.X : nullptr, p->ncs, n, ell, s0, ns,
+                                             p1_slots_per_block(p, ns, batch), nullptr, w.U, batch, p->twL2,
+                                             p->twA, s, packed ? nullptr : &ain))
                             throw HipFail{hipErrorInvalidValue};
                     }
                     PhaseTimer t(tm, THX_PHASE_ROW, s);
