@@ -1551,11 +1551,11 @@ constexpr int nthreads() { return fft_threads(M, NB, R); }
 //   z = l~_s o X (zero-padded to L) -> FFT -> . that -> IFFT -> acc += l~_s o y
 // with `that` = FFT(symbol)/L.  The accumulator stays in registers, in the
 // forward-input layout that the inverse transform returns to.
-template <typename T, int L, int R>
+template <typename T, int L, int R, bool AIN>
 __global__ __launch_bounds__((nthreads<L, 1, R>())) void k_toep_lds(
     const cpx<T> *__restrict__ X, int64_t nc, int64_t n, const cpx<T> *__restrict__ ell, int S,
     int spg, const cpx<T> *__restrict__ that, const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ W,
-    int64_t batch)
+    int64_t batch, AlphaIn ain)
 {
     using F = RegFFT<T, L, 1, nthreads<L, 1, R>(), R>;
     constexpr int E = F::E;
@@ -1583,14 +1583,21 @@ __global__ __launch_bounds__((nthreads<L, 1, R>())) void k_toep_lds(
     // slot loop (fewer registers; measured faster for FP64; in FP32 needed at
     // 8192 points, where the hoisted values spill).
     auto opq = [](const cpx<T> *q) { return sizeof(T) == 8 || L >= 8192 ? opaque_ptr(q) : q; };
+    // input lanes from the packed X, or (AIN) formed from the vector itself
+    int64_t abase = 0, aN = -1;
+    if constexpr (AIN) vec_of(VecRef{ain.off, ain.deg}, b, ain.ld, ain.N0, abase, aN);
     for (int s = s0; s < s1; ++s) {
         const cpx<T> *es = opq(ell + (int64_t)s * nc);
-        const cpx<T> *Xb = opq(X + b * nc);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int pos, c;
             F::in_pos(e, pos, c);
-            v[e] = (e % RF <= RH && pos < n) ? cdiag(es[pos], Xb[pos]) : cpx<T>{0, 0};
+            if (e % RF <= RH && pos < n) {
+                if constexpr (AIN) v[e] = cdiag(es[pos], x_lane<T>(ain.k, opaque_ptr(ain.alpha + abase), aN, pos));
+                else v[e] = cdiag(es[pos], opq(X + b * nc)[pos]);
+            } else {
+                v[e] = cpx<T>{0, 0};
+            }
         }
         F::forward(v, lds, tw);
         const cpx<T> *ts = opq(that);
@@ -1645,45 +1652,55 @@ __global__ __launch_bounds__((nthreads<L, 1>())) void k_fft_lds(const cpx<T> *in
 
 template <typename T, int L, int R>
 static void run_toep_lds(const void *X, int64_t nc, int64_t n, const void *ell, int S, int spg, int G,
-                         const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
+                         const void *that, const void *tw, void *W, int64_t batch, hipStream_t s,
+                         const AlphaIn &ain)
 {
     dim3 grid((unsigned)G, (unsigned)batch);
-    k_toep_lds<T, L, R><<<grid, nthreads<L, 1, R>(), 0, s>>>((const cpx<T> *)X, nc, n, (const cpx<T> *)ell,
-                                                               S, spg, (const cpx<T> *)that,
-                                                               (const cpx<T> *)tw, (cpx<T> *)W, batch);
+    if (ain.alpha)
+        k_toep_lds<T, L, R, true><<<grid, nthreads<L, 1, R>(), 0, s>>>(
+            (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, S, spg, (const cpx<T> *)that, (const cpx<T> *)tw,
+            (cpx<T> *)W, batch, ain);
+    else
+        k_toep_lds<T, L, R, false><<<grid, nthreads<L, 1, R>(), 0, s>>>(
+            (const cpx<T> *)X, nc, n, (const cpx<T> *)ell, S, spg, (const cpx<T> *)that, (const cpx<T> *)tw,
+            (cpx<T> *)W, batch, ain);
 }
 
 template <typename T, int L>
 static void run_toep_lds_r(int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S, int spg,
-                           int G, const void *that, const void *tw, void *W, int64_t batch, hipStream_t s)
+                           int G, const void *that, const void *tw, void *W, int64_t batch, hipStream_t s,
+                           const AlphaIn &ain)
 {
-    if (radix == 16) run_toep_lds<T, L, 16>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
-    else run_toep_lds<T, L, 8>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
+    if (radix == 16) run_toep_lds<T, L, 16>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s, ain);
+    else run_toep_lds<T, L, 8>(X, nc, n, ell, S, spg, G, that, tw, W, batch, s, ain);
 }
 
 template <typename T>
 bool launch_toep_lds(int64_t L, int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S,
                      int spg, int G, const void *that, const void *tw, void *W, int64_t batch,
-                     hipStream_t s)
+                     hipStream_t s, const AlphaIn *ainp)
 {
     if (n > L / 2 + 1 || n > nc) return false; // the kernel loads and keeps positions below L/2 + 1 only
     if (radix != 8 && radix != 16) return false;
+    if (!X && !(ainp && ainp->alpha)) return false;
+    AlphaIn ain{};
+    if (ainp) ain = *ainp;
     switch (L) {
-#define THX_CASE(LL) case LL: run_toep_lds_r<T, LL>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s); return true;
+#define THX_CASE(LL) case LL: run_toep_lds_r<T, LL>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s, ain); return true;
         THX_CASE(64) THX_CASE(128) THX_CASE(256) THX_CASE(512) THX_CASE(1024) THX_CASE(2048)
         THX_CASE(4096)
 #undef THX_CASE
     case 8192:
         if constexpr (sizeof(T) == 4) {
-            run_toep_lds_r<T, 8192>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s);
+            run_toep_lds_r<T, 8192>(radix, X, nc, n, ell, S, spg, G, that, tw, W, batch, s, ain);
             return true;
         }
         return false;
     default: return false;
     }
 }
-template bool launch_toep_lds<double>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
-template bool launch_toep_lds<float>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t);
+template bool launch_toep_lds<double>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t, const AlphaIn *);
+template bool launch_toep_lds<float>(int64_t, int, const void *, int64_t, int64_t, const void *, int, int, int, const void *, const void *, void *, int64_t, hipStream_t, const AlphaIn *);
 
 template <typename T>
 bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale, hipStream_t s)

@@ -30,6 +30,16 @@ struct KindDesc {
     int64_t band;        // >= 0: A_jk = 0 for k - j > band (identity stages); -1: full
 };
 
+// The vectors of an execution in place of a packed X: lane a of vector b is
+// (D2 alpha) at indices 2a, 2a+1 (parity kinds) or (D2 alpha)_a twice, as the
+// pack step would form it; off / deg and ld / N0 as for launch_pack.
+struct AlphaIn {
+    KindDesc k;
+    const int64_t *off, *deg;
+    const double *alpha;
+    int64_t ld, N0;
+};
+
 // Device state of the pivoted Cholesky (two independent parts at most).
 // Pivots are chosen and the factorisation stopped on the weighted residual
 // diagonal w_i d_i, w_i = |D1_j D2_j| (the diagonal of S H S with
@@ -211,7 +221,7 @@ constexpr int64_t MP_LMAX = (int64_t)1 << 22;
 template <typename T>
 bool launch_toep_lds(int64_t L, int radix, const void *X, int64_t nc, int64_t n, const void *ell, int S,
                      int slots_per_group, int G, const void *that, const void *tw, void *Wpart,
-                     int64_t batch, hipStream_t s);
+                     int64_t batch, hipStream_t s, const AlphaIn *ain = nullptr);
 // plain forward FFT of one length-L complex array in LDS (symbol transform), scaled
 template <typename T>
 bool launch_fft_lds(int64_t L, const void *in, void *out, const void *tw, double scale,
@@ -225,15 +235,6 @@ struct MultiPassGeom {
 template <typename T> MultiPassGeom multipass_geom(int64_t L, int64_t row = 0);
 // true when the three-pass kernels are built for rows of L1 points and columns of L / L1
 bool multipass_ok(int64_t L, int64_t L1);
-// The vectors of an execution in place of a packed X: lane a of vector b is
-// (D2 alpha) at indices 2a, 2a+1 (parity kinds) or (D2 alpha)_a twice, as the
-// pack step would form it; off / deg and ld / N0 as for launch_pack.
-struct AlphaIn {
-    KindDesc k;
-    const int64_t *off, *deg;
-    const double *alpha;
-    int64_t ld, N0;
-};
 // P1: U[s][b] = column FFTs (+ twiddle) of ell_s o X[b] (or of `src` when ell == nullptr),
 // `spb` consecutive slots per workgroup; with `ain` the lanes of X are formed from
 // the vectors themselves (X unused, no pack step)

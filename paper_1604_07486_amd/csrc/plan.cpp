@@ -1079,14 +1079,16 @@ int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const 
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
     // For one vector up to L = 2^17 the separate forward column pass, one slot
     // per workgroup, forms its input lanes from the vector itself: one launch
-    // fewer (measured 2 us faster at N = 2^16 in both precisions).  Otherwise the
+    // fewer (measured 2 us faster at N = 2^16 in both precisions, and 1.4 us at
+    // N = 2048 on the single-workgroup path: 15.5 -> 14.1 us).  Otherwise the
     // lanes are packed first: at 2^20 re-forming them for each of 45 slots cost
     // 8 us more than the pack launch, and on the 4096-polynomial batch 1.2-1.6 ms
     // more (members at odd offsets take two 8-byte loads per lane in every slot).
-    // The single-workgroup path, the fused row pass and the forward pass with
-    // slot groups (which keeps its tile's lanes in registers across the slots)
-    // always read them packed.
-    const bool packed = !(p->path == 2 && !(p->fuse_p1 && p->geom.L2 <= 4) && p->p1_blocks <= 0 &&
+    // The single-workgroup path forms them itself under the same rule; the fused
+    // row pass and the forward pass with slot groups (which keeps its tile's
+    // lanes in registers across the slots) always read them packed.
+    const bool packed = !((p->path == 1 || (p->path == 2 && !(p->fuse_p1 && p->geom.L2 <= 4) &&
+                                            p->p1_blocks <= 0)) &&
                           p->L <= ((int64_t)1 << 17) && batch == 1) ||
                         p->S <= 0;
     const AlphaIn ain{p->kd, off, deg, alpha, ld, N};
@@ -1101,8 +1103,8 @@ int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const 
             const int spg = (p->S + Gt - 1) / Gt;
             G = (p->S + spg - 1) / spg;
             PhaseTimer t(tm, THX_PHASE_TOEP_LDS, s);
-            if (!launch_toep_lds<T>(p->L, p->lds_radix, w.X, p->ncs, n, ell, p->S, spg, G, p->that, p->twL,
-                                    w.Wp, batch, s))
+            if (!launch_toep_lds<T>(p->L, p->lds_radix, packed ? w.X : nullptr, p->ncs, n, ell, p->S, spg, G,
+                                    p->that, p->twL, w.Wp, batch, s, packed ? nullptr : &ain))
                 throw HipFail{hipErrorInvalidValue};
         } else {
             const MultiPassGeom &g = p->geom;
