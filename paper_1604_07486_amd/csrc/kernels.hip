@@ -1914,16 +1914,24 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
             const int64_t a = a1_0 + c + (int64_t)L1 * a2;
             xv[e] = live(e, a) ? xin(a) : cpx<T>{0, 0};
         }
-        for (int sl = s0; sl < s1; ++sl) {
+        // the next slot's l~ tile is loaded while this slot is transformed
+        cpx<T> ev[F::E];
+        auto load_ell = [&](int sl) {
             const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
-            cpx<T> v[F::E];
 #pragma unroll
             for (int e = 0; e < F::E; ++e) {
                 int a2, c;
                 F::in_pos(e, a2, c);
                 const int64_t a = a1_0 + c + (int64_t)L1 * a2;
-                v[e] = live(e, a) ? cdiag(es[a], xv[e]) : cpx<T>{0, 0};
+                ev[e] = live(e, a) ? es[a] : cpx<T>{0, 0};
             }
+        };
+        if (s0 < s1) load_ell(s0);
+        for (int sl = s0; sl < s1; ++sl) {
+            cpx<T> v[F::E];
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) v[e] = cdiag(ev[e], xv[e]);
+            if (sl + 1 < s1) load_ell(sl + 1);
             transform_store(v, sl);
             __syncthreads(); // the next slot's transform reuses the LDS
         }
