@@ -140,3 +140,28 @@ def test_execute_varlen_malformed_offsets(thx):
     assert int(skipped.item()) == 2
     bars.check(got[:2001], oracle.matvec("leg2cheb", al), al, 1e-13, 0, entry_scale=1.0, label="member 0 ")
     bars.check(got[2001:2502], oracle.matvec("leg2cheb", a1), a1, 1e-13, 0, entry_scale=1.0, label="member 1 ")
+
+
+# one member (the kernels then form their input lanes from the vector itself)
+# starting at an odd index: 8-byte-aligned coefficients, on the single-workgroup
+# path, the three-pass path, cheb2leg's direct row 0 and a unit step; the
+# element before the member stays untouched
+@pytest.mark.parametrize("kind,params,N,prec", [(0, (), 3000, 0), (0, (), 3001, 1), (0, (), 30000, 0),
+                                                (0, (), 30001, 1), (1, (), 20000, 0), (2, (1.5, 0.5), 9001, 0)])
+def test_execute_varlen_single_member_odd_offset(thx, kind, params, N, prec):
+    import torch
+    tol = 1e-15 if prec == 0 else 1e-7
+    plan = thx.Plan(kind, N, tol, prec, params=params)
+    al = inputs.coeffs(N, 1.0, seed=N + kind)
+    flat = np.concatenate([[3.0], al])
+    offs = np.array([1, N + 2], dtype=np.int64)
+    print(f"[case] varlen one member at offset 1 kind={kind} N={N} prec={prec} path={plan.path}", flush=True)
+    a = _dev(flat)
+    b = torch.full_like(a, 7.0)
+    plan.execute_varlen(a, b, torch.from_numpy(offs).to("cuda:0"))
+    torch.cuda.synchronize()
+    got = b.cpu().numpy()
+    assert got[0] == 7.0
+    ref = oracle.matvec(bars.ORACLE_NAME[kind], al, params)
+    bars.check(got[1:], ref, al, 1e-13 if prec == 0 else 5e-6, kind, params,
+               entry_scale=2 * N + 1 if kind == 2 else 1.0, label=f"path {plan.path} ")
