@@ -1214,7 +1214,8 @@ static_assert(DENSE_PAD % DN_BK == 0, "dense tiling");
 // every CU a workgroup of 256 outputs.  BM vectors per workgroup: 64 (wave w
 // owns vectors 16w..16w+15 and every output tile), or 32 (two waves per group of
 // 16 vectors, each taking every other output tile, so both keep the same
-// triangular share).
+// triangular share).  Compiled for three waves per SIMD at 32 vectors (134
+// registers; left to itself the compiler took 144 + 64 and ran two).
 template <int BN, int BM = 64>
 __global__ __launch_bounds__(DN_NT) __attribute__((amdgpu_waves_per_eu(BM == 32 ? 3 : 2))) void k_dense(const double *__restrict__ At, int npad, VecRef vr,
                                                  const double *__restrict__ alpha, int64_t ld,
@@ -1391,8 +1392,10 @@ __global__ void k_split_matrix(const double *__restrict__ At, int npad, v4u *__r
 // vectors to give every CU a workgroup of 256 outputs).  Per chunk of 32 k the
 // workgroup stages the matrix parts of its JB columns in LDS (coalesced 16-byte
 // loads, read into registers one chunk ahead); each wave reads the alpha values
-// of its own 16 vectors straight into operand registers (also one chunk ahead),
-// splits them, and runs 8 products per output tile of the chunk.
+// of its own 16 vectors straight into operand registers (two chunks ahead),
+// splits them, and runs 8 products per output tile of the chunk.  Compiled for
+// two waves per SIMD at 256 outputs (left to itself the compiler took 256 + 64
+// registers and ran one).
 template <int JB>
 __global__ __launch_bounds__(DB_NT) __attribute__((amdgpu_waves_per_eu(JB == 256 ? 2 : 4))) void k_dense_bf16(const v4u *__restrict__ Bp, int npad, VecRef vr,
                                                       const double *__restrict__ alpha, int64_t ld,
