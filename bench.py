@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline timed loop (for profiler runs)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="in --headline-only mode, run the plan's default launch shapes (the same kernels in "
+                         "every run: counter passes that must be combined)")
     ap.add_argument("--prec", choices=["fp64", "fp32", "tail32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
     ap.add_argument("--only", choices=["batched", "config5", "sweep", "config1", "dense"], default=None,
@@ -167,6 +170,10 @@ def write_traffic(fetch_db, write_db, run_log, out=None):
             per.setdefault(k, {}).setdefault(key, []).append(v)
         per.setdefault("_factor", {})[key] = factor
     fac = per.pop("_factor")
+    odd = sorted(k for k, vals in per.items() if len(vals) != 2)
+    if odd:
+        raise SystemExit(f"the two counter runs timed different kernels {odd}: profile a plan with fixed "
+                         "launch shapes (--no-autotune)")
     rows_md, row = [], None
     for k, vals in sorted(per.items(), key=lambda kv: -sum(kv[1].get("fetch", [0]))):
         f = sum(vals["fetch"]) / len(vals["fetch"]) * 1024 * fac["fetch"]
@@ -178,10 +185,13 @@ def write_traffic(fetch_db, write_db, run_log, out=None):
                        f"{(algo or 0) / 1e6:.1f} | {ratio} |")
         if ph == "row" and (row is None or f + w > row[1] + row[2]):
             row = (k, f, w, algo, vals)
+    tuned = info.get("autotuned", True)
     cmd = ("rocprofv3 --pmc {c} -d $OUT/pmc/{p}_{lg}_{c} -o pmc -- python3 $R/bench.py --headline-only --steps 3 "
-           "--warmup 1 --copy-calibration --prec {p} --log2n {lg}")
+           "--warmup 1 --copy-calibration --prec {p} --log2n {lg}" + ("" if tuned else " --no-autotune"))
     lines = [
-        f"# HBM traffic per launch of the timed loop, leg2cheb N=2^{lg} {prec} plan (autotuned for one vector)",
+        f"# HBM traffic per launch of the timed loop, leg2cheb N=2^{lg} {prec} plan "
+        + ("(autotuned for one vector)" if tuned else
+           f"(default launch shapes, geometry {info.get('fft_geometry')}: the same kernels in both counter runs)"),
         "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
         "# dispatches between trace markers 1 and 2; factors = bytes of the 512 MiB device copy in the",
         "# same run / counter.  Commands (repo root $R, output directory $OUT, from /tmp, TMPDIR=/tmp):",
@@ -676,7 +686,8 @@ def main():
     if args.headline_only:
         prec = {"fp64": thx.FP64, "fp32": thx.FP32_BULK, "tail32": thx.FP64_TAIL32}[args.prec]
         plan = thx.Plan(thx.LEG2CHEB, N, 1e-7 if prec == thx.FP32_BULK else 1e-15, prec)
-        plan.autotune(1)
+        if not args.no_autotune:
+            plan.autotune(1)
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase="row")
         parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
         copy_gbs = copy_bandwidth(torch) if args.copy_calibration else None
@@ -685,6 +696,8 @@ def main():
         pb = {ph: phase_bytes(ph, es, S, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
               for ph in ("col_fwd", "row", "col_inv")}
         print(json.dumps({"headline_only": True, "prec": args.prec, "log2n": args.log2n, "ms_per_step": ms,
+                          "autotuned": not args.no_autotune,
+                          "fft_geometry": list(plan.fft_geometry()) if plan.path == 2 else None,
                           "copy_gbs": copy_gbs, "K": plan.rank, "tail_slots": plan.tail_slots, "L": plan.fft_length,
                           "row_ms_avg": phase_avg(tim).get("row"),
                           "row_kernel": row_kernel_name(plan) if prec == thx.FP64 else None,
