@@ -66,6 +66,11 @@ constexpr int fft_threads(int M, int NB, int RMAX, int maxnt = 1024)
 #endif
 __device__ __forceinline__ int lds_pad(int i) { return THX_LDS_PAD ? i + (i >> 4) : i; }
 constexpr int lds_padded(int n) { return THX_LDS_PAD ? n + (n >> 4) : n; }
+// For b >= 0 and a stride S that is a multiple of 16, the padded index of
+// b + k S is lds_pad(b) + k lds_padded(S): the elements a thread moves in one
+// exchange then sit at constant offsets from one base address, and the
+// compiler folds them into the LDS instructions' offset fields.
+constexpr bool lds_linear(int S) { return !THX_LDS_PAD || S % 16 == 0; }
 
 // w_R^m = exp(-+ 2 pi i m / R) for the constant twiddles inside a radix-R DFT
 template <typename T, int R, int m, bool INV>
@@ -299,8 +304,15 @@ struct RegFFT {
                 for (int p = 0; p < PB; ++p) {
                     const int w = (int)threadIdx.x + NT * p;
                     const int c = w % NB, j = w / NB;
+                    constexpr int S = (M / R) * NB; // position j + r M / R of sequence c
+                    if constexpr (lds_linear(S)) {
+                        const cpx<T> *src = lds + lds_pad(j * NB + c);
 #pragma unroll
-                    for (int r = 0; r < R; ++r) v[p * R + r] = lds[lds_pad((j + r * (M / R)) * NB + c)];
+                        for (int r = 0; r < R; ++r) v[p * R + r] = src[r * lds_padded(S)];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) v[p * R + r] = lds[lds_pad(j * NB + c + r * S)];
+                    }
                 }
                 __syncthreads();
             }
@@ -317,8 +329,15 @@ struct RegFFT {
                     const int w = (int)threadIdx.x + NT * p;
                     const int c = w % NB, j = w / NB;
                     const int base = (j / Ns) * Ns * R + (j % Ns);
+                    constexpr int S = Ns * NB; // position base + q Ns of sequence c
+                    if constexpr (lds_linear(S)) {
+                        cpx<T> *dst = lds + lds_pad(base * NB + c);
 #pragma unroll
-                    for (int q = 0; q < R; ++q) lds[lds_pad((base + q * Ns) * NB + c)] = v[p * R + q];
+                        for (int q = 0; q < R; ++q) dst[q * lds_padded(S)] = v[p * R + q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < R; ++q) lds[lds_pad(base * NB + c + q * S)] = v[p * R + q];
+                    }
                 }
                 __syncthreads();
             }
