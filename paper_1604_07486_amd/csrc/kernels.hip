@@ -2157,14 +2157,32 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
     cpx<T> acc[EH], accm{0, 0}, v[E];
 #pragma unroll
     for (int h = 0; h < EH; ++h) acc[h] = cpx<T>{0, 0};
-    const int s1 = min(nslots, (g + 1) * spg);
-    for (int sl = g * spg; sl < s1; ++sl) {
+    const int s0 = g * spg, s1 = min(nslots, (g + 1) * spg);
+    auto load_tile = [&](int sl, cpx<T> *dst) {
         const cpx<T> *Ub = U + ((int64_t)sl * batch + b) * L1 * L2;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             int k2, c;
             F::out_pos(e, k2, c);
-            v[e] = ld_stream(Ub + a1_0 + c + (int64_t)L1 * k2);
+            dst[e] = ld_stream(Ub + a1_0 + c + (int64_t)L1 * k2);
+        }
+    };
+    // In single precision a tile carries half the bytes per value, so the
+    // next slot's tile is loaded while this slot is transformed, which keeps
+    // as many bytes in flight per wave as the double-precision pass has (in
+    // double precision, and for columns of 3 * 2^m, the second tile does not
+    // fit in 128 registers).
+    constexpr bool PF = sizeof(T) == 4 && L2 % 3 != 0;
+    cpx<T> vn[PF ? E : 1];
+    if constexpr (PF)
+        if (s0 < s1) load_tile(s0, vn);
+    for (int sl = s0; sl < s1; ++sl) {
+        if constexpr (PF) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = vn[e];
+            if (sl + 1 < s1) load_tile(sl + 1, vn);
+        } else {
+            load_tile(sl, v);
         }
         const cpx<T> *es = ell + (int64_t)(slot0 + sl) * nc;
         if constexpr (EARLY) {
