@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="in --headline-only mode, run the plan's default launch shapes (the same kernels in "
                          "every run: counter passes that must be combined)")
+    ap.add_argument("--shapes", nargs=2, type=int, metavar=("ROW", "P1_BLOCKS"), default=None,
+                    help="in --headline-only mode, fix the three-pass row length and the forward column pass's "
+                         "workgroups per launch (0: one slot per workgroup) instead of autotuning, so that "
+                         "counter passes that must be combined run the kernels the autotuner picks")
     ap.add_argument("--prec", choices=["fp64", "fp32", "tail32"], default="fp64",
                     help="precision of the headline loop in --headline-only mode")
     ap.add_argument("--only", choices=["batched", "config5", "sweep", "config1", "dense"], default=None,
@@ -185,13 +189,20 @@ def write_traffic(fetch_db, write_db, run_log, out=None):
                        f"{(algo or 0) / 1e6:.1f} | {ratio} |")
         if ph == "row" and (row is None or f + w > row[1] + row[2]):
             row = (k, f, w, algo, vals)
-    tuned = info.get("autotuned", True)
+    tuned, shapes = info.get("autotuned", True), info.get("shapes")
+    fixed = f" --shapes {shapes[0]} {shapes[1]}" if shapes else " --no-autotune"
     cmd = ("rocprofv3 --pmc {c} -d $OUT/pmc/{p}_{lg}_{c} -o pmc -- python3 $R/bench.py --headline-only --steps 3 "
-           "--warmup 1 --copy-calibration --prec {p} --log2n {lg}" + ("" if tuned else " --no-autotune"))
+           "--warmup 1 --copy-calibration --prec {p} --log2n {lg}" + ("" if tuned else fixed))
+    if tuned:
+        how = "(autotuned for one vector)"
+    elif shapes:
+        p1 = f"{shapes[1]} workgroups per launch" if shapes[1] > 0 else "one slot per workgroup"
+        how = (f"(launch shapes fixed at those the autotuner picks, geometry {info.get('fft_geometry')}, forward "
+               f"column pass {p1}: the same kernels in both counter runs)")
+    else:
+        how = f"(default launch shapes, geometry {info.get('fft_geometry')}: the same kernels in both counter runs)"
     lines = [
-        f"# HBM traffic per launch of the timed loop, leg2cheb N=2^{lg} {prec} plan "
-        + ("(autotuned for one vector)" if tuned else
-           f"(default launch shapes, geometry {info.get('fft_geometry')}: the same kernels in both counter runs)"),
+        f"# HBM traffic per launch of the timed loop, leg2cheb N=2^{lg} {prec} plan " + how,
         "# Counters in KiB per dispatch from rocprofv3 --pmc, one counter per run, averaged over the",
         "# dispatches between trace markers 1 and 2; factors = bytes of the 512 MiB device copy in the",
         "# same run / counter.  Commands (repo root $R, output directory $OUT, from /tmp, TMPDIR=/tmp):",
@@ -685,8 +696,11 @@ def main():
 
     if args.headline_only:
         prec = {"fp64": thx.FP64, "fp32": thx.FP32_BULK, "tail32": thx.FP64_TAIL32}[args.prec]
+        if args.shapes:   # read by the library when the plan is created
+            os.environ["THX_ROW_LEN"], os.environ["THX_P1_BLOCKS"] = (str(v) for v in args.shapes)
         plan = thx.Plan(thx.LEG2CHEB, N, 1e-7 if prec == thx.FP32_BULK else 1e-15, prec)
-        if not args.no_autotune:
+        tuned = not (args.no_autotune or args.shapes)
+        if tuned:
             plan.autotune(1)
         ms, tim = time_plan(thx, torch, plan, a, b, args.steps, args.warmup, phase="row")
         parts = phase_breakdown(torch, plan, a, b, max(5, args.steps // 5))
@@ -696,8 +710,9 @@ def main():
         pb = {ph: phase_bytes(ph, es, S, N // 2 + 1, plan.fft_length, plan.partial_groups(1))
               for ph in ("col_fwd", "row", "col_inv")}
         print(json.dumps({"headline_only": True, "prec": args.prec, "log2n": args.log2n, "ms_per_step": ms,
-                          "autotuned": not args.no_autotune,
+                          "autotuned": tuned, "shapes": args.shapes,
                           "fft_geometry": list(plan.fft_geometry()) if plan.path == 2 else None,
+                          "p1_blocks": plan.p1_blocks if plan.path == 2 else None,
                           "copy_gbs": copy_gbs, "K": plan.rank, "tail_slots": plan.tail_slots, "L": plan.fft_length,
                           "row_ms_avg": phase_avg(tim).get("row"),
                           "row_kernel": row_kernel_name(plan) if prec == thx.FP64 else None,
@@ -849,7 +864,7 @@ def main():
         "autotune_ms": round(tune_ms, 2),
         "fft_geometry": list(plan.fft_geometry()) if plan.path == 2 else None,
         "launch_shape": {"lds_blocks": plan.launch_shape()[0], "p3_blocks": plan.launch_shape()[1],
-                         "partial_groups": Gc},
+                         "p1_blocks": plan.p1_blocks, "partial_groups": Gc},
         "copy_gbs_measured": round(copy_gbs, 1),
         "step_hbm_gbs_algorithmic": round(step_bytes / (ms * 1e-3) / 1e9, 1),
         "phases_ms_avg": phase_avg(parts),

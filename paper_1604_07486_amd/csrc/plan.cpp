@@ -1486,7 +1486,7 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
                                  f64 ? mp_row_long<double>() : mp_row_long<float>(),
                                  f64 ? mp_row_xl<double>() : mp_row_xl<float>()};
         int64_t best_row = p->geom.L1;
-        int best_p3 = p->p3_blocks;
+        int best_p3 = p->p3_blocks, best_p1 = 0;
         float tb = 1e30f;
         bool best_fuse = false;
         for (int64_t row : rows) {
@@ -1494,28 +1494,35 @@ void tune_stage(thx_plan *p, const double *alpha, double *beta, int64_t batch, h
             configure_rows(p, row, s);
             if (p->geom.L1 != row) continue;
             p->p1_blocks = 0;
+            float trow = 1e30f;
+            int row_p3 = p->p3_blocks;
+            bool row_fuse = false;
             for (int fuse = 0; fuse < (p->geom.L2 <= 4 ? 2 : 1); ++fuse) {
                 p->fuse_p1 = fuse != 0;
                 for (int p3 : {512, 1024, 2048}) {
                     p->p3_blocks = p3;
                     const float t = time_launches(run, s);
-                    if (t < tb) tb = t, best_row = row, best_p3 = p3, best_fuse = p->fuse_p1;
+                    if (t < trow) trow = t, row_p3 = p3, row_fuse = p->fuse_p1;
+                }
+            }
+            if (trow < tb) tb = trow, best_row = row, best_p3 = row_p3, best_fuse = row_fuse, best_p1 = 0;
+            // then, for this row length, the separate forward column pass with
+            // several slots per workgroup (when that still leaves enough
+            // workgroups): its tiles differ per row length, so it is timed
+            // with each
+            if (!row_fuse) {
+                p->p3_blocks = row_p3;
+                p->fuse_p1 = false;
+                for (int p1 : {8192, 2048}) {
+                    p->p1_blocks = p1;
+                    const float t = time_launches(run, s);
+                    if (t < tb) tb = t, best_row = row, best_p3 = row_p3, best_fuse = false, best_p1 = p1;
                 }
             }
         }
         configure_rows(p, best_row, s);
         p->p3_blocks = best_p3;
         p->fuse_p1 = best_fuse;
-        // then the separate forward column pass: several slots per workgroup when
-        // that still leaves enough workgroups
-        int best_p1 = 0;
-        if (!p->fuse_p1) {
-            for (int p1 : {8192, 2048}) {
-                p->p1_blocks = p1;
-                const float t = time_launches(run, s);
-                if (t < tb) tb = t, best_p1 = p1;
-            }
-        }
         p->p1_blocks = best_p1;
         // single-precision tail on (with its inverse-pass workgroups) or off
         // (off: those slots in double precision)
