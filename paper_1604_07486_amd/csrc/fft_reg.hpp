@@ -218,33 +218,31 @@ __device__ __forceinline__ void dft(cpx<T> *v)
     }
 }
 
-// twiddle factors w^{e1 r}, r = 1..R-1, from the table tw[e] = w_M^e (e < M):
-// w^1, w^2, w^4, w^8 are read and every other power is a product of at most
-// four of them; the factors are formed just before use to keep few registers
-// live.
+// x times w (forward) or conj(w) (inverse)
 template <typename T, bool INV>
 __device__ __forceinline__ void twmul(cpx<T> &x, cpx<T> w)
 {
     x = INV ? cmulc(x, w) : cmul(x, w);
 }
 
-template <typename T, int R, bool INV>
-__device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restrict__ tw, int e1)
+// Twiddle factors w^r, r = 1..R-1, of one radix-R butterfly (w = w_M^{e1},
+// from the table tw[e] = w_M^e, e < M): w^1, w^2, w^4, w^8 (as far as R needs
+// them) come from pw(k) = w^(2^k) and every other power is a product of at most
+// four of them; the factors are formed just before use to keep few registers
+// live.
+template <typename T, int R, bool INV, typename PW>
+__device__ __forceinline__ void twiddle_products(cpx<T> *v, PW pw)
 {
-    // The exponent is made opaque so that the table reads stay here: hoisted out
-    // of a caller's loop over ranks they would pin every stage's twiddles in
-    // registers and force spills.
-    asm volatile("" : "+v"(e1));
-    const cpx<T> w1 = tw[e1];
+    const cpx<T> w1 = pw(0);
     twmul<T, INV>(v[1], w1);
     if constexpr (R == 2) return;
-    const cpx<T> w2 = tw[2 * e1];
+    const cpx<T> w2 = pw(1);
     twmul<T, INV>(v[2], w2);
     if constexpr (R == 3) return;
     const cpx<T> w3 = cmul(w1, w2);
     twmul<T, INV>(v[3], w3);
     if constexpr (R == 4) return;
-    const cpx<T> w4 = tw[4 * e1];
+    const cpx<T> w4 = pw(2);
     twmul<T, INV>(v[4], w4);
     if constexpr (R == 5) return;
     twmul<T, INV>(v[5], cmul(w1, w4));
@@ -252,7 +250,7 @@ __device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restri
     const cpx<T> w7 = cmul(w3, w4);
     twmul<T, INV>(v[7], w7);
     if constexpr (R == 8) return;
-    const cpx<T> w8 = tw[8 * e1];
+    const cpx<T> w8 = pw(3);
     twmul<T, INV>(v[8], w8);
     twmul<T, INV>(v[9], cmul(w1, w8));
     twmul<T, INV>(v[10], cmul(w2, w8));
@@ -263,7 +261,39 @@ __device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restri
     twmul<T, INV>(v[15], cmul(w7, w8));
 }
 
-template <typename T, int M, int NB, int NT, int RMAX = 16>
+// twiddles read from the table tw[e] = w_M^e where they are used
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_twiddles(cpx<T> *v, const cpx<T> *__restrict__ tw, int e1)
+{
+    // The exponent is made opaque so that the table reads stay here: hoisted out
+    // of a caller's loop over ranks they would pin every stage's twiddles in
+    // registers and force spills.
+    asm volatile("" : "+v"(e1));
+    twiddle_products<T, R, INV>(v, [&](int k) { return tw[e1 * (1 << k)]; });
+}
+
+// Table reads of one butterfly's twiddles issued ahead of their use
+// (apply_loaded_twiddles then forms the products from them).
+template <int R> constexpr int tw_reads() { return R == 2 ? 1 : (R <= 4 ? 2 : (R <= 8 ? 3 : 4)); }
+
+template <typename T, int R>
+__device__ __forceinline__ void load_twiddles(cpx<T> *w, const cpx<T> *__restrict__ tw, int e1)
+{
+    asm volatile("" : "+v"(e1));
+#pragma unroll
+    for (int k = 0; k < tw_reads<R>(); ++k) w[k] = tw[e1 * (1 << k)];
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_loaded_twiddles(cpx<T> *v, const cpx<T> *w)
+{
+    twiddle_products<T, R, INV>(v, [&](int k) { return w[k]; });
+}
+
+// PREF: each stage issues the table reads of the next stage's twiddles before
+// its own exchange and arithmetic, so that their latency is hidden behind them
+// (costs the registers that hold them; off by default).
+template <typename T, int M, int NB, int NT, int RMAX = 16, bool PREF = false>
 struct RegFFT {
     static constexpr int E = M * NB / NT;
     static constexpr int NS = nstages(M, RMAX);
@@ -290,14 +320,37 @@ struct RegFFT {
         pos = w / NB + q * (M / R_LAST);
     }
 
+    // table reads of one thread's twiddles in stage s (at least one slot)
     template <bool INV, int s>
-    __device__ static __forceinline__ void stages(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
+    static constexpr int stage_tw_reads()
+    {
+        if constexpr (s >= NS) return 1;
+        else return (E / stage_radix<INV>(M, s, RMAX)) * tw_reads<stage_radix<INV>(M, s, RMAX)>();
+    }
+    template <bool INV, int s>
+    __device__ static __forceinline__ void load_stage_twiddles(cpx<T> *w, const cpx<T> *__restrict__ tw)
+    {
+        constexpr int R = stage_radix<INV>(M, s, RMAX);
+        constexpr int Ns = stage_ns<INV>(M, s, RMAX);
+#pragma unroll
+        for (int p = 0; p < E / R; ++p) {
+            const int j = ((int)threadIdx.x + NT * p) / NB;
+            load_twiddles<T, R>(w + p * tw_reads<R>(), tw, (j % Ns) * (M / (Ns * R)));
+        }
+    }
+
+    // `wpre`: this stage's twiddle reads, issued by the previous stage (PREF)
+    template <bool INV, int s>
+    __device__ static __forceinline__ void stages(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw,
+                                                  const cpx<T> *wpre)
     {
         if constexpr (s < NS) {
             constexpr int R = stage_radix<INV>(M, s, RMAX);
             constexpr int Ns = stage_ns<INV>(M, s, RMAX);
             constexpr int PB = E / R; // butterflies per thread
             static_assert(PB * R == E, "radix divides the per-thread count");
+            cpx<T> wnext[stage_tw_reads<INV, s + 1>()];
+            if constexpr (PREF && s + 1 < NS) load_stage_twiddles<INV, s + 1>(wnext, tw);
             if constexpr (s > 0) {
                 // values are in LDS at the positions written by the previous stage
 #pragma unroll
@@ -320,7 +373,10 @@ struct RegFFT {
             for (int p = 0; p < PB; ++p) {
                 const int w = (int)threadIdx.x + NT * p;
                 const int j = w / NB;
-                if constexpr (Ns > 1) apply_twiddles<T, R, INV>(v + p * R, tw, (j % Ns) * (M / (Ns * R)));
+                if constexpr (Ns > 1) {
+                    if constexpr (PREF) apply_loaded_twiddles<T, R, INV>(v + p * R, wpre + p * tw_reads<R>());
+                    else apply_twiddles<T, R, INV>(v + p * R, tw, (j % Ns) * (M / (Ns * R)));
+                }
                 dft<T, R, INV>(v + p * R);
             }
             if constexpr (s + 1 < NS) {
@@ -341,7 +397,7 @@ struct RegFFT {
                 }
                 __syncthreads();
             }
-            stages<INV, s + 1>(v, lds, tw);
+            stages<INV, s + 1>(v, lds, tw, wnext);
         }
     }
 
@@ -350,12 +406,12 @@ struct RegFFT {
     // use of `lds` only if it writes it itself.
     __device__ static __forceinline__ void forward(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
     {
-        stages<false, 0>(v, lds, tw);
+        stages<false, 0>(v, lds, tw, nullptr);
     }
     // inverse (unnormalised): output layout -> input layout
     __device__ static __forceinline__ void inverse(cpx<T> *v, cpx<T> *lds, const cpx<T> *__restrict__ tw)
     {
-        stages<true, 0>(v, lds, tw);
+        stages<true, 0>(v, lds, tw, nullptr);
     }
 };
 

@@ -1993,7 +1993,10 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int 
                                                                 cpx<T> *__restrict__ out, T scale)
 {
     constexpr int NT = p2_threads<T, L1>();
-    using F = RegFFT<T, L1, 1, NT, RMAX_ROW>;
+    // double precision reads each stage's twiddles a stage ahead (its rows are
+    // held to two waves per SIMD by LDS, so the registers are there; in single
+    // precision they would cost a wave per SIMD)
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>;
     __shared__ cpx<T> lds[F::LDS];
     int k2, sb;
     xcd_map(blockIdx.x, L2, nsb, k2, sb);
