@@ -1785,7 +1785,10 @@ constexpr int mp_nt()
     if constexpr (col_mixed<L2>()) return mp_tc<T, L2>() * L2 / col_e<L2>();
     else return nthreads<L2, mp_tc<T, L2>()>();
 }
-template <typename T, int L2> using ColFFT = RegFFT<T, L2, mp_tc<T, L2>(), mp_nt<T, L2>(), col_rmax<L2>()>;
+// PREF (twiddle reads a stage ahead) only for columns of 2^m: the mixed-radix
+// columns' 12 or 20 values per thread leave no registers for them
+template <typename T, int L2, bool PREF = false>
+using ColFFT = RegFFT<T, L2, mp_tc<T, L2>(), mp_nt<T, L2>(), col_rmax<L2>(), PREF && !col_mixed<L2>()>;
 
 // columns the three-pass kernels are built for: 2^m (2 ... 1024), 3 * 2^m (6 ... 768)
 // or 5 * 2^m (10 ... 640; a column of 5 would start its inverse with an odd radix,
@@ -1844,7 +1847,9 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
 {
     constexpr int TC = mp_tc<T, L2>();
     constexpr int NT = mp_nt<T, L2>();
-    using F = ColFFT<T, L2>;
+    // twiddle reads a stage ahead, except with slot groups (their registers
+    // hold the tile's input across slots)
+    using F = ColFFT<T, L2, !SG>;
     constexpr int64_t L = (int64_t)L1 * L2;
     __shared__ cpx<T> lds[F::LDS];
     constexpr int tiles = L1 / TC;
@@ -1956,7 +1961,7 @@ __device__ __forceinline__ void p2_row(cpx<T> *v, cpx<T> *lds, int k2, cpx<T> *_
                                        const cpx<T> *__restrict__ twA, const cpx<T> *__restrict__ twL2)
 {
     constexpr int NT = p2_threads<T, L1>();
-    using F = RegFFT<T, L1, 1, NT, RMAX_ROW>;
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>; // as in k_mp_p2
     F::forward(v, lds, twL1);
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -2132,7 +2137,10 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) __attribute__((amdgpu_waves_per_e
     const cpx<T> *__restrict__ twL2)
 {
     constexpr int TC = mp_tc<T, L2>();
-    using F = ColFFT<T, L2>;
+    // twiddle reads a stage ahead in double precision; in single precision
+    // the next slot's tile is read ahead instead (both together measured
+    // slower at columns of 512)
+    using F = ColFFT<T, L2, sizeof(T) == 8>;
     constexpr int E = F::E;
     // Outputs kept: positions a < n <= L/2 + 1 of each sequence.  In the
     // inverse's output layout, register slot e holds column position
