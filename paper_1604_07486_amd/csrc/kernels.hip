@@ -2002,7 +2002,7 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int 
     constexpr int NT = p2_threads<T, L1>();
     // double precision reads each stage's twiddles a stage ahead (its rows are
     // held to two waves per SIMD by LDS, so the registers are there; in single
-    // precision they would cost a wave per SIMD)
+    // precision they cost a wave per SIMD: rows of 8192 measured 0.48 -> 0.65 ms)
     using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>;
     __shared__ cpx<T> lds[F::LDS];
     int k2, sb;
