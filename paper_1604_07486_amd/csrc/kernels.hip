@@ -1963,7 +1963,7 @@ __device__ __forceinline__ void p2_row(cpx<T> *v, cpx<T> *lds, int k2, cpx<T> *_
                                        const cpx<T> *__restrict__ twA, const cpx<T> *__restrict__ twL2)
 {
     constexpr int NT = p2_threads<T, L1>();
-    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>; // as in k_mp_p2
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>;
     F::forward(v, lds, twL1);
 #pragma unroll
     for (int e = 0; e < F::E; ++e) {
@@ -2000,13 +2000,18 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int 
                                                                 cpx<T> *__restrict__ out, T scale)
 {
     constexpr int NT = p2_threads<T, L1>();
-    // double precision reads each stage's twiddles a stage ahead (its rows are
-    // held to two waves per SIMD by LDS, so the registers are there; in single
-    // precision they cost a wave per SIMD: rows of 8192 measured 0.48 -> 0.65 ms)
-    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, sizeof(T) == 8>;
-    __shared__ cpx<T> lds[F::LDS];
+    // twiddles read a stage ahead (in single precision this needs the
+    // registers freed by the epilogue's twiddles in LDS: with those formed on
+    // every lane it cost a wave per SIMD, rows of 8192 0.48 -> 0.65 ms)
+    using F = RegFFT<T, L1, 1, NT, RMAX_ROW, true>;
+    constexpr int RF = F::R_FIRST, PG = F::E / RF;
+    // the exchange area, then the RF workgroup-uniform epilogue twiddles
+    __shared__ cpx<T> lds[F::LDS + RF];
     int k2, sb;
     xcd_map(blockIdx.x, L2, nsb, k2, sb);
+    // w_L^{r k2 L1/RF}, formed once per workgroup instead of on every lane (the
+    // transforms' barriers order these writes before the epilogue's reads)
+    if (full && (int)threadIdx.x < RF) lds[F::LDS + threadIdx.x] = tw_L<T, L1>(twA, twL2, (int)threadIdx.x * (L1 / RF) * k2);
     const int64_t L = (int64_t)L1 * L2;
     cpx<T> *row = U + (int64_t)sb * L + (int64_t)k2 * L1;
     cpx<T> v[F::E];
@@ -2036,14 +2041,13 @@ __global__ __launch_bounds__((p2_threads<T, L1>())) void k_mp_p2(cpx<T> *U, int 
     F::inverse(v, lds, twL1);
     // Conjugate twiddle w_L^{-a1 k2} with a1 = j_p + r L1/RF (j_p = threadIdx.x
     // + NT p): a per-thread factor w_L^{j_p k2} times the workgroup-uniform
-    // w_L^{r k2 L1/RF}, so only one table pair per group is gathered.
-    constexpr int RF = F::R_FIRST, PG = F::E / RF;
+    // w_L^{r k2 L1/RF} (from LDS), so only one table pair per group is gathered.
     cpx<T> bp[PG];
 #pragma unroll
     for (int p = 0; p < PG; ++p) bp[p] = tw_L<T, L1>(twA, twL2, ((int)threadIdx.x + NT * p) * k2);
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        const cpx<T> sr = tw_L<T, L1>(twA, twL2, r * (L1 / RF) * k2);
+        const cpx<T> sr = lds[F::LDS + r];
 #pragma unroll
         for (int p = 0; p < PG; ++p) {
             const int a1 = (int)threadIdx.x + NT * p + r * (L1 / RF);
