@@ -1862,13 +1862,12 @@ __global__ __launch_bounds__((mp_nt<T, L2>())) void k_mp_p1(
     const int sg = (int)((blockIdx.x / tiles) % nsg);
     const int64_t b = blockIdx.x / (tiles * nsg);
     const cpx<T> *Xb = X ? X + b * nc : nullptr;
-    // lanes formed from the vector itself when no packed X is given (one slot per
-    // workgroup only: the slot-group form reads X, its registers are taken)
+    // lanes formed from the vector itself when no packed X is given (with slot
+    // groups once per workgroup, before the slot loop)
     int64_t abase = 0, aN = -1;
-    if (!SG && ain.alpha) vec_of(VecRef{ain.off, ain.deg}, b, ain.ld, ain.N0, abase, aN);
+    if (ain.alpha) vec_of(VecRef{ain.off, ain.deg}, b, ain.ld, ain.N0, abase, aN);
     auto xin = [&](int64_t a) -> cpx<T> {
-        if constexpr (SG) return Xb[a];
-        else return ain.alpha ? x_lane<T>(ain.k, ain.alpha + abase, aN, a) : Xb[a];
+        return ain.alpha ? x_lane<T>(ain.k, ain.alpha + abase, aN, a) : Xb[a];
     };
     // slots e with e mod RF > RF/2 hold positions above L/2: zero padding
     auto live = [&](int e, int64_t a) { return e % RF <= RF / 2 && a < n; };
@@ -2284,7 +2283,7 @@ bool launch_mp_p1(const MultiPassGeom &g, const void *X, int64_t nc, int64_t n, 
 {
     if (ell && (n > g.L1 * g.L2 / 2 + 1 || n > nc)) return false; // zero padding above L/2 is assumed
     if (spb < 1 || nslots < 1 || (spb > 1 && !ell)) return false;
-    if (ell && !X && (spb > 1 || !(ainp && ainp->alpha))) return false; // slot groups read a packed X
+    if (ell && !X && !(ainp && ainp->alpha)) return false; // input lanes: packed X or the vector
     AlphaIn ain{};
     if (ainp && ell) ain = *ainp;
     if (g.L1 == mp_row_short<T>())

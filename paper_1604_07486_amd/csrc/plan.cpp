@@ -1077,20 +1077,24 @@ int run_slots(thx_plan *p, const Ws &w, thx_plan *tm, const int64_t *off, const 
 {
     const int64_t n = p->kd.parity ? N / 2 + 1 : N + 1;
     const void *ell = p->prec == THX_FP64 ? (const void *)p->ell64 : (const void *)p->ell32;
-    // For one vector up to L = 2^17 the separate forward column pass, one slot
-    // per workgroup, forms its input lanes from the vector itself: one launch
-    // fewer (measured 2 us faster at N = 2^16 in both precisions, and 1.4 us at
-    // N = 2048 on the single-workgroup path: 15.5 -> 14.1 us).  Otherwise the
-    // lanes are packed first: at 2^20 re-forming them for each of 45 slots cost
-    // 8 us more than the pack launch, and on the 4096-polynomial batch 1.2-1.6 ms
-    // more (members at odd offsets take two 8-byte loads per lane in every slot).
-    // The single-workgroup path forms them itself under the same rule; the fused
-    // row pass and the forward pass with slot groups (which keeps its tile's
-    // lanes in registers across the slots) always read them packed.
-    const bool packed = !((p->path == 1 || (p->path == 2 && !(p->fuse_p1 && p->geom.L2 <= 4) &&
-                                            p->p1_blocks <= 0)) &&
-                          p->L <= ((int64_t)1 << 17) && batch == 1) ||
-                        p->S <= 0;
+    // For one vector the forward column pass forms its input lanes from the
+    // vector itself and the pack launch is skipped: with one slot per workgroup
+    // up to L = 2^17 (measured 2 us faster at N = 2^16 in both precisions, and
+    // 1.4 us at N = 2048 on the single-workgroup path, which follows the same
+    // rule: 15.5 -> 14.1 us), and in double precision with slot groups at any
+    // length (each workgroup forms its tile's lanes once for its slots; 2^20
+    // 0.770 -> 0.766 ms).  Above 2^17, re-forming the lanes for each of 45
+    // slots cost 8 us more than the pack launch at 2^20, and on the
+    // 4096-polynomial batch 1.2-1.6 ms more (members at odd offsets take two
+    // 8-byte loads per lane in every slot); single-precision lanes are half the
+    // bytes of the vector they come from, so slot groups read them packed there
+    // (2^22: 1.019 -> 1.02-1.04 ms formed from the vector); batches and the
+    // fused row pass read them packed.
+    const bool fused = p->path == 2 && p->fuse_p1 && p->geom.L2 <= 4;
+    const bool groups = sizeof(T) == 8 && p->path == 2 &&
+                        p1_slots_per_block(p, (int)std::min<int64_t>(w.U_slots, p->S), batch) > 1;
+    const bool packed = p->S <= 0 || batch != 1 || fused || (p->path != 1 && p->path != 2) ||
+                        (p->L > ((int64_t)1 << 17) && !groups);
     const AlphaIn ain{p->kd, off, deg, alpha, ld, N};
     if (packed) {
         PhaseTimer t(tm, THX_PHASE_PACK, s);
